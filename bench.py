@@ -1,0 +1,186 @@
+"""Benchmark of the compressed Deep Potential MD step on one MI355X.
+
+Workload: 108,000-atom FCC copper (30x30x30 cells, a = 3.634 A, Gaussian
+displacements sigma = 0.05 A), seeded random weights of the copper model
+(embedding 32-64-128, fitting 240-240-240, rcut 8 A, sel 192), velocity
+Verlet NVE at dt = 1 fs, neighbor list (2 A skin) rebuilt every 10 steps.
+One step = half kick + drift (+ rebuild) + energy/forces/virial + half kick.
+
+    python bench.py [--gpus 1] [--steps 100] [--warmup 10]
+
+Prints one JSON line: atom-steps/s of the FP32 compressed path (value), the
+FP64 compressed path beside it, per-kernel times from HIP events recorded on
+the launch stream, the roofline of the dominant kernel, and the FP64 CPU
+oracle timed on a bounded sample of the same workload on the host cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published peaks, TFLOP/s (dense)
+    ("alu", "f32"): 157.3, ("alu", "f64"): 78.6,
+    ("mfma", "f32"): 157.3, ("mfma", "f64"): 78.6, ("mfma", "bf16"): 2500.0,
+}
+HBM_PEAK_GBS = 8000.0
+FIT_FLOP_PER_ATOM = 2 * (2048 * 240 + 240 * 240 * 2)   # one pass (fwd or input-grad)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--ncell", type=int, default=30)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def run_nve(P, model, x0, v0, box, steps, warmup, precision, mode=0):
+    import torch
+    x = torch.tensor(x0, dtype=torch.float64, device="cuda")
+    v = torch.tensor(v0, dtype=torch.float64, device="cuda")
+    nl = P.NeighborList(model, x, box, skin=2.0)
+    if warmup:
+        P.nve_run(model, nl, x, v, box, 63.546, 1.0, warmup, rebuild_every=10, precision=precision, mode=mode)
+    torch.cuda.synchronize()
+    from paper_2201_01446_amd import _lib
+    _lib.timers_read()
+    _lib.timers_enable(True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record()
+    th = P.nve_run(model, nl, x, v, box, 63.546, 1.0, steps, rebuild_every=10, precision=precision, mode=mode)
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    _lib.timers_enable(False)
+    kern = _lib.timers_read()
+    ms = t0.elapsed_time(t1)
+    return dict(ms=ms, wall=wall, thermo=th.cpu().numpy(), kernels=kern, x=x, nl=nl)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the per-GPU share is the "
+              "108,000-atom kernel measured at --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2201_01446_amd as P
+    import synth
+
+    cfg = synth.copper_model_config()
+    params = synth.model_params(cfg)
+    model = P.Model(cfg, params).tabulate(0.7, 0.01, 1.5, 0.1)
+    x0, box = synth.copper(args.ncell, 0.05, synth.SEED_CFG[2])
+    v0 = synth.maxwell_boltzmann(len(x0), 330.0)
+    N = len(x0)
+    K, W = args.steps, args.warmup
+
+    res32 = run_nve(P, model, x0, v0, box, K, W, P.FP32)
+    res64 = None if args.no_fp64 else run_nve(P, model, x0, v0, box, K, W, P.FP64)
+
+    # neighbor statistics of the final configuration (for the FLOP counts)
+    d = P.descriptor(model, res32["nl"], res32["x"], precision=P.FP32)
+    sum_nei = int(d["nnei"].sum().item())
+
+    def roofline(res, dt):
+        kern = res["kernels"]
+        steps = K
+        flops = {
+            "emb_fwd": (sum_nei * 128 * 9 * 2, "alu"),
+            "emb_bwd": (sum_nei * 128 * 18 * 2, "alu"),
+            "fit_gemm": (N * FIT_FLOP_PER_ATOM * 2, "mfma"),
+        }
+        per = {}
+        for name, (tot_ms, cnt) in kern.items():
+            per[name] = dict(avg_ms=tot_ms / max(cnt, 1), launches=cnt, total_ms=tot_ms)
+        dom = max((n for n in per if n in flops), key=lambda n: per[n]["total_ms"])
+        fl, bound = flops[dom]
+        launches_per_step = per[dom]["launches"] / steps
+        per_launch = fl / launches_per_step
+        achieved = per_launch / (per[dom]["avg_ms"] * 1e-3) / 1e12
+        peak = PEAK[(bound, dt)]
+        return dom, dict(bound=bound, achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
+                         frac=round(achieved / peak, 4), traffic=None, kernel=dom,
+                         per_launch_flop=per_launch), per
+
+    dom, roof, per32 = roofline(res32, "f32")
+    value = N * K / (res32["ms"] * 1e-3)
+    ms_step = res32["ms"] / K
+
+    # FP32 energy conservation over the run
+    th = res32["thermo"]
+    etot = th[:, 0] + th[:, 1]
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(cfg, params, x0, box, args.cpu_seconds)
+
+    out = {
+        "metric": "atom-steps/s on 1 GPU, compressed DP MD step (FP32), force RMSE <= 1e-3 eV/A",
+        "value": round(value, 1),
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: seeded FCC Cu + Gaussian displacements, seeded random weights",
+        "config": {"workload": f"Cu FCC {args.ncell}^3 cells ({N} atoms), sigma 0.05 A, NVE dt 1 fs, "
+                               "nlist skin 2 A rebuilt every 10 steps, compressed (stride 0.01, tail 0.1)",
+                   "natoms": N, "precision": "fp32", "mode": "compressed"},
+        "ns_per_day": round(value / N * 86400 * 1e-6, 3),
+        "roofline": roof,
+        "kernels_fp32": {k: round(v["avg_ms"], 4) for k, v in per32.items()},
+        "energy_drift_fp32_eV_per_atom": float((etot[-1] - etot[0]) / N),
+        "mean_neighbors": sum_nei / N,
+    }
+    if res64 is not None:
+        v64 = N * K / (res64["ms"] * 1e-3)
+        _, roof64, per64 = roofline(res64, "f64")
+        out["fp64"] = {"value": round(v64, 1), "ms_per_step": round(res64["ms"] / K, 4),
+                       "roofline": roof64, "kernels": {k: round(v["avg_ms"], 4) for k, v in per64.items()}}
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    print(json.dumps(out))
+
+
+def cpu_baseline(cfg, params, x, box, seconds):
+    """The FP64 oracle (untabulated, as it stands) timed on a bounded sample:
+    energy and force contributions of a random subset of the atoms of the
+    same configuration; rate = sampled atoms / wall time."""
+    import oracle
+    rng = np.random.default_rng(0)
+    probe = rng.choice(len(x), 64, replace=False).astype(np.int32)
+    t = time.perf_counter()
+    oracle.evaluate(cfg, params, x, box, centers=probe)
+    tp = time.perf_counter() - t
+    n = int(min(len(x), max(64, 64 * seconds / max(tp, 1e-3))))
+    sample = rng.choice(len(x), n, replace=False).astype(np.int32)
+    t = time.perf_counter()
+    oracle.evaluate(cfg, params, x, box, centers=sample)
+    dt = time.perf_counter() - t
+    return {"value": round(n / dt, 2), "unit": "atom-steps/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"E_i and force contributions of {n} random atoms of the {len(x)}-atom workload "
+                      f"(untabulated FP64 oracle, {dt:.1f} s)"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,188 @@
+/*
+ * dp.h -- C-ABI of the MI355X (gfx950) compressed Deep Potential force step.
+ *
+ * The library computes, for one configuration of atoms, the Deep Potential
+ * energy E = sum_i E_i, the forces F_i = -grad_i E and the virial, as the
+ * paper defines them in Sec. 2.1 (Eqs. 1-5), with the embedding net replaced
+ * by its fifth-order-polynomial tabulation (Sec. 3.2) and evaluated fused
+ * with the R^T G contraction, padded neighbors skipped (Sec. 3.3, 3.4).
+ *
+ * Conventions for every entry point:
+ *   - Arrays named *_d are DEVICE pointers owned by the caller (for example
+ *     the storage of torch tensors on the current HIP device).  They are
+ *     borrowed until the work enqueued on `stream` has completed.  Arrays
+ *     named *_h are HOST pointers, read before the call returns.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it; entry points do not synchronise unless their
+ *     comment says so.
+ *   - Coordinates are Angstrom, energies eV, forces eV/A; all results are
+ *     FP64 whatever the precision mode.
+ *   - Boxes are 9 doubles on the HOST, row vectors a, b, c; only
+ *     orthorhombic boxes (off-diagonals zero) are accepted.  box_h == NULL
+ *     means an open (non-periodic) cluster.
+ *   - Return value: DP_OK or a negative dp_status.  On error nothing has been
+ *     enqueued, and dp_last_error() describes the cause.
+ *   - Handles (dp_model, dp_nlist) are owned by the library and released by
+ *     their *_destroy call.  A model may serve several streams at once once
+ *     its table is built; each configuration needs its own dp_nlist (the
+ *     nlist also owns that configuration's scratch buffers).
+ */
+#ifndef DP_H
+#define DP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DP_OK = 0,
+    DP_ERR_ARG = -1,         /* a bad argument (NULL, size, shape)              */
+    DP_ERR_HIP = -2,         /* a HIP runtime call failed                       */
+    DP_ERR_OOM = -3,         /* device allocation failed                        */
+    DP_ERR_CAPACITY = -4,    /* a neighbor-list or cell capacity was exceeded   */
+    DP_ERR_UNSUPPORTED = -5, /* a valid request this build does not implement   */
+    DP_ERR_STATE = -6,       /* call order violated (e.g. no table yet)         */
+    DP_ERR_NONFINITE = -7    /* a non-finite energy was produced                */
+} dp_status;
+
+typedef enum {
+    DP_FP64 = 0,        /* everything in double precision                            */
+    DP_FP32 = 1,        /* table, contraction, fitting net in FP32 (FP32 MFMA)       */
+    DP_MIXED_BF16 = 2   /* as FP32, fitting-net GEMMs on BF16 MFMA, FP32 accumulate */
+} dp_precision;
+
+typedef enum {
+    DP_COMPRESSED = 0,  /* tabulated embedding fused with the contraction (Sec. 3) */
+    DP_PLAIN = 1        /* embedding net evaluated layer by layer, padded to sel   */
+} dp_mode;
+
+/* Model hyper-parameters (Sec. 2.1 and the physical-systems section).
+ *   ntypes      must be 1 (one element, copper);
+ *   rcut        cut-off R_c (A); rcut_smth: start of the gate w(r) (A);
+ *   sel         N_m: neighbors kept per atom (the nearest sel within rcut);
+ *   emb         embedding widths d1, 2 d1, 4 d1 (M = emb[2]); emb[2] must be 128;
+ *   m_lt        M<, columns of G kept in G< (Eq. 2); must be 16;
+ *   fit         fitting-net hidden widths (each at most 256);
+ *   desc_scale  factor multiplying R^T G (1/sel by default);
+ *   switch_kind 0: gate 1-10u^3+15u^4-6u^5, 1: (cos(pi u)+1)/2, u=(r-rs)/(rc-rs). */
+typedef struct {
+    int ntypes;
+    double rcut;
+    double rcut_smth;
+    int sel;
+    int emb[3];
+    int m_lt;
+    int fit[3];
+    double desc_scale;
+    int switch_kind;
+} dp_model_config;
+
+typedef struct dp_model dp_model;
+typedef struct dp_nlist dp_nlist;
+
+/* Creates a model from the flat FP64 parameter vector params_h (HOST,
+ * nparams doubles, copied).  Layout, row-major [fan_in][fan_out]:
+ *   embedding  W0[1][d1] b0[d1] W1[d1][2d1] b1[2d1] W2[2d1][4d1] b2[4d1]
+ *   fitting    V1[M< * M][f1] c1[f1] V2[f1][f2] c2[f2] V3[f2][f3] c3[f3]
+ *              w4[f3] b4[1]
+ * Embedding layers follow Eqs. 4-5 (tanh; the shortcut (x,x) is the
+ * concatenation [x, x]); fitting layers are tanh with a shortcut where the
+ * input and output widths match, and a linear output (Sec. 2.1).
+ * Allocates device memory on the current device.  Errors: DP_ERR_ARG on a
+ * bad config or count, DP_ERR_UNSUPPORTED for ntypes != 1 or other widths. */
+dp_status dp_model_create(const dp_model_config *cfg, const double *params_h, size_t nparams,
+                          dp_model **out);
+dp_status dp_model_destroy(dp_model *model);
+
+/* Builds the coefficient table of the embedding net (Sec. 3.2): on each
+ * interval the M quintics whose value, first and second derivative match the
+ * net at both nodes.  Intervals of width `stride` cover [0, s_max), then
+ * intervals of width `tail_stride` cover [s_max, tail_max) (tail_max ==
+ * s_max: no tail).  A polynomial is written in the offset t = s - x_lo from
+ * its interval's left node; s past tail_max is clamped to tail_max and
+ * counted (dp_nlist_stats).  Runs on `stream`, in FP64 on the device; the
+ * FP32 copy is derived from it.  Must precede every compressed dp_compute. */
+dp_status dp_tabulate(dp_model *model, double s_max, double stride, double tail_max,
+                      double tail_stride, void *stream);
+
+/* Copies the FP64 table to the host: coef_h[(theta * M + eta) * 6 + xi] is
+ * the coefficient of t^xi of column eta on interval theta.  *n_int receives
+ * the interval count (coef_h may be NULL to query it).  Synchronises. */
+dp_status dp_table_download(dp_model *model, double *coef_h, int *n_int);
+
+/* Neighbor list with a skin (paper Sec. 2.1 L_Rc(i); the MD protocol keeps a
+ * 2 A buffer): for every atom i all (j, periodic image) with
+ * |x_j + n L - x_i| < rcut + skin, sorted by that distance, stored on the
+ * device.  Images are handled for any box edge >= (rcut + skin) / 2, so cells
+ * smaller than the cut-off sphere see several images of each atom (and of
+ * the atom itself).  *inout: NULL creates a list, else it is rebuilt in place
+ * (reallocated if natoms grew).  types_d (natoms int32) must be all 0.
+ * Synchronises once to check the capacity flags; DP_ERR_CAPACITY when an
+ * atom has more than 1024 candidates. */
+dp_status dp_build_nlist(dp_model *model, int natoms, const double *coords_d, const int *types_d,
+                         const double *box_h, double skin, dp_nlist **inout, void *stream);
+dp_status dp_nlist_destroy(dp_nlist *nlist);
+
+/* Energy, forces and virial of the configuration the list was built for, at
+ * coordinates coords_d (natoms x 3), which may have moved by less than
+ * skin / 2 since the build.  Neighbors beyond rcut are skipped; when more
+ * than sel remain, the sel nearest are kept (counted in dp_nlist_stats).
+ * Outputs (device, FP64; NULL skips):
+ *   energy_d[1]        E = sum_i E_i
+ *   force_d[natoms*3]  F_i = -dE/dx_i (overwritten)
+ *   virial_d[9]        W = -sum_i sum_j r_ij (x) dE_i/dr_ij, r_ij = x_j - x_i
+ *   atom_energy_d[natoms]  E_i
+ * Passing force_d == NULL and virial_d == NULL runs the forward pass only.
+ * mode DP_PLAIN evaluates the embedding net layer by layer over sel padded
+ * rows (the untabulated baseline); DP_COMPRESSED needs dp_tabulate first. */
+dp_status dp_compute(dp_model *model, dp_nlist *nlist, int natoms, const double *coords_d,
+                     const int *types_d, const double *box_h, int mode, int precision,
+                     double *energy_d, double *force_d, double *virial_d,
+                     double *atom_energy_d, void *stream);
+
+/* Intermediate results for testing: per atom the number of neighbors used
+ * (nnei_d, int32), T = desc_scale * R^T G (T_d, natoms x 4 x M, row k of
+ * the 4 environment columns) and D = (T<)^T T (D_d, natoms x M< x M), all
+ * FP64 copies; any may be NULL. */
+dp_status dp_descriptor(dp_model *model, dp_nlist *nlist, int natoms, const double *coords_d,
+                        const double *box_h, int mode, int precision, int *nnei_d, double *T_d,
+                        double *D_d, void *stream);
+
+/* Sticky counters of the list since its last build (synchronises):
+ * max_nei: most neighbors within rcut seen for one atom; n_sel_overflow:
+ * atoms that had more than sel; n_table_oob: look-ups past the table end;
+ * n_cap_overflow: atoms whose candidate list was truncated at build. */
+dp_status dp_nlist_stats(dp_nlist *nlist, int *max_nei, int *n_sel_overflow, int *n_table_oob,
+                         int *n_cap_overflow);
+
+/* Velocity-Verlet NVE (the MD protocol of the physical-systems section):
+ * nsteps of half kick, drift, [neighbor rebuild every rebuild_every steps],
+ * force, half kick, all on `stream` in FP64 (positions x_d and velocities
+ * v_d, natoms x 3, updated in place; A and A/fs).  mass in amu, dt_fs in fs.
+ * thermo_d (device, nsteps+1 rows of 2 doubles: potential and kinetic
+ * energy, row 0 = start) may be NULL.  The nlist is rebuilt at the start.
+ * Synchronises at the end to check the capacity flags. */
+dp_status dp_nve_run(dp_model *model, dp_nlist **nlist, int natoms, double *x_d, double *v_d,
+                     const int *types_d, const double *box_h, double mass, double dt_fs,
+                     int nsteps, int rebuild_every, double skin, int mode, int precision,
+                     double *thermo_d, void *stream);
+
+/* Kernel timing for measurement: while enabled, every kernel launch of the
+ * library is bracketed by HIP events recorded on the stream it is launched
+ * on.  dp_timers_read synchronises on those events, returns per kernel name
+ * (names: max_names slots of 32 chars) the summed duration in ms and the
+ * launch count, and clears the records. */
+dp_status dp_timers_enable(int on);
+dp_status dp_timers_read(int max_names, char *names, double *total_ms, int *counts, int *n_names);
+
+/* Message of the last failed call on this thread ("" if none); valid until
+ * the next call on the thread. */
+const char *dp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DP_H */

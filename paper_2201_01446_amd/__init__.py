@@ -1,0 +1,10 @@
+"""Compressed Deep Potential force step on MI355X (gfx950).
+
+The computation lives in libdp.so (hand-written HIP kernels behind the C-ABI
+of include/dp.h).  This package is the thin Python side: `Model`,
+`NeighborList`, `compute`, `nve_run`, the autograd function in
+`autograd`, and the serving loop in `serve`.  PyTorch provides device memory
+and streams only.
+"""
+from .api import (COMPRESSED, FP32, FP64, MIXED_BF16, PLAIN, DPError, Model, NeighborList,  # noqa: F401
+                  compute, descriptor, nve_run)

@@ -1,0 +1,526 @@
+// abi.hip -- the extern "C" entry points of libdp (declared in include/dp.h):
+// argument checks, handle lifetimes, device allocations, and the order of
+// kernel launches.  No arithmetic of the model lives here.
+
+#include "dp_internal.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace dp {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+dp_status fail(dp_status st, const std::string &msg)
+{
+    g_err = msg;
+    return st;
+}
+
+dp_status hip_fail(hipError_t e, const char *what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? DP_ERR_OOM : DP_ERR_HIP;
+}
+
+dp_status step_check(const char *name, hipStream_t st)
+{
+    static const bool sync = [] {
+        const char *e = std::getenv("DP_SYNC_CHECK");
+        return e && e[0] == '1';
+    }();
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && sync) {
+        e = hipStreamSynchronize(st);
+        if (e == hipSuccess) e = hipGetLastError();
+    }
+    if (e != hipSuccess) return hip_fail(e, name);
+    return DP_OK;
+}
+
+namespace {
+
+template <typename T>
+dp_status upload(T **dst, const std::vector<T> &src)
+{
+    DP_HIP(hipMalloc((void **)dst, sizeof(T) * src.size()));
+    DP_HIP(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
+    return DP_OK;
+}
+
+// float -> bfloat16 bits, round to nearest even
+uint16_t bf16_bits(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+dp_status upload_fit(FitWeights &w, const std::vector<double> *mats, int prec)
+{
+    // mats: V1 [2048][256], V1t [256][2048], V2, V2t, V3, V3t [256][256]
+    void **dst[6] = {&w.V1, &w.V1t, &w.V2, &w.V2t, &w.V3, &w.V3t};
+    for (int k = 0; k < 6; k++) {
+        const std::vector<double> &m = mats[k];
+        size_t n = m.size();
+        if (prec == DP_FP64) {
+            DP_HIP(hipMalloc(dst[k], n * 8));
+            DP_HIP(hipMemcpy(*dst[k], m.data(), n * 8, hipMemcpyHostToDevice));
+        } else if (prec == DP_FP32) {
+            std::vector<float> f(n);
+            for (size_t i = 0; i < n; i++) f[i] = (float)m[i];
+            DP_HIP(hipMalloc(dst[k], n * 4));
+            DP_HIP(hipMemcpy(*dst[k], f.data(), n * 4, hipMemcpyHostToDevice));
+        } else {
+            std::vector<uint16_t> b(n);
+            for (size_t i = 0; i < n; i++) b[i] = bf16_bits((float)m[i]);
+            DP_HIP(hipMalloc(dst[k], n * 2));
+            DP_HIP(hipMemcpy(*dst[k], b.data(), n * 2, hipMemcpyHostToDevice));
+        }
+    }
+    return DP_OK;
+}
+
+void free_fit(FitWeights &w)
+{
+    void *p[6] = {w.V1, w.V1t, w.V2, w.V2t, w.V3, w.V3t};
+    for (void *q : p)
+        if (q) (void)hipFree(q);
+    w = FitWeights{};
+}
+
+size_t expected_params(const dp_model_config &c)
+{
+    size_t d1 = c.emb[0], d2 = c.emb[1], d3 = c.emb[2];
+    size_t f1 = c.fit[0], f2 = c.fit[1], f3 = c.fit[2];
+    size_t nD = (size_t)c.m_lt * d3;
+    return d1 + d1 + d1 * d2 + d2 + d2 * d3 + d3 + nD * f1 + f1 + f1 * f2 + f2 + f2 * f3 + f3 + f3 + 1;
+}
+
+bool box_ok(const double *box, double L[3])
+{
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++)
+            if (a != b && box[3 * a + b] != 0.0) return false;
+    for (int a = 0; a < 3; a++) {
+        L[a] = box[4 * a];
+        if (!(L[a] > 0.0) || !std::isfinite(L[a])) return false;
+    }
+    return true;
+}
+
+void free_nlist_arrays(dp_nlist *nl)
+{
+    void *p[] = {nl->cell_cnt, nl->cell_atoms, nl->wpos, nl->wrap, nl->cnt, nl->nei, nl->shift,
+                 nl->flags, nl->ws, nl->ws_plain, nl->force_tmp, nl->scal};
+    for (void *q : p)
+        if (q) (void)hipFree(q);
+}
+
+// (Re)allocates the list for natoms atoms in box (NULL: open); no launch.
+dp_status prepare_nlist(const dp_model *m, int natoms, const double *box, double skin, dp_nlist **inout)
+{
+    if (natoms <= 0) return fail(DP_ERR_ARG, "natoms must be positive");
+    if (natoms >= (1 << 25)) return fail(DP_ERR_UNSUPPORTED, "at most 2^25 - 1 atoms");
+    if (!(skin >= 0.0) || !std::isfinite(skin)) return fail(DP_ERR_ARG, "skin must be >= 0");
+    dp_nlist *nl = *inout;
+    bool fresh = nl == nullptr;
+    if (fresh) nl = new dp_nlist();
+    int dev = 0;
+    DP_HIP(hipGetDevice(&dev));
+    nl->device = dev;
+    nl->rc_build = m->cfg.rcut + skin;
+    double rcs = nl->rc_build;
+    int cap;
+    if (box) {
+        double L[3];
+        if (!box_ok(box, L)) {
+            if (fresh) delete nl;
+            return fail(DP_ERR_UNSUPPORTED, "box must be orthorhombic with positive edges");
+        }
+        for (int a = 0; a < 3; a++)
+            if (L[a] < 0.5 * rcs) {
+                if (fresh) delete nl;
+                return fail(DP_ERR_UNSUPPORTED, "box edge shorter than (rcut + skin) / 2");
+            }
+        nl->periodic = true;
+        for (int a = 0; a < 3; a++) {
+            nl->L[a] = L[a];
+            nl->nc[a] = (int)std::floor(L[a] / (0.5 * rcs));
+            if (nl->nc[a] < 1) nl->nc[a] = 1;
+        }
+        double vol = L[0] * L[1] * L[2];
+        double expect = natoms / vol * 4.18879020478639 * rcs * rcs * rcs;   // 4/3 pi r^3
+        cap = (int)round_up((long)std::ceil(1.3 * expect + 64.0), 64);
+        long ncell = (long)nl->nc[0] * nl->nc[1] * nl->nc[2];
+        int per = (int)std::ceil((double)natoms / ncell);
+        int cellcap = (int)round_up(3 * per + 8, 8);
+        if (cellcap < nl->cellcap) cellcap = nl->cellcap;   // keep a grown capacity
+        if ((size_t)ncell * cellcap > nl->ncell_alloc) {
+            if (nl->cell_atoms) DP_HIP(hipFree(nl->cell_atoms));
+            if (nl->cell_cnt) DP_HIP(hipFree(nl->cell_cnt));
+            nl->cell_atoms = nullptr;
+            nl->cell_cnt = nullptr;
+            DP_HIP(hipMalloc(&nl->cell_atoms, sizeof(int) * (size_t)ncell * cellcap));
+            DP_HIP(hipMalloc(&nl->cell_cnt, sizeof(int) * (size_t)ncell));
+            nl->ncell_alloc = (size_t)ncell * cellcap;
+        }
+        // cell_cnt must hold ncell entries even if ncell * cellcap fit before
+        if ((size_t)ncell > nl->ncell_alloc) return fail(DP_ERR_STATE, "cell grid bookkeeping");
+        nl->cellcap = cellcap;
+    } else {
+        nl->periodic = false;
+        for (int a = 0; a < 3; a++) {
+            nl->L[a] = 0.0;
+            nl->nc[a] = 1;
+        }
+        cap = (int)round_up(natoms, 64);
+    }
+    if (cap < 128) cap = 128;
+    if (cap > kCapMax) cap = kCapMax;
+    bool grow = natoms > nl->alloc_atoms || cap > nl->cap;
+    if (grow) {
+        int alloc = natoms > nl->alloc_atoms ? natoms : nl->alloc_atoms;
+        int capn = cap > nl->cap ? cap : nl->cap;
+        void *p[] = {nl->wpos, nl->wrap, nl->cnt, nl->nei, nl->shift, nl->force_tmp};
+        for (void *q : p)
+            if (q) DP_HIP(hipFree(q));
+        DP_HIP(hipMalloc(&nl->wpos, sizeof(double) * 3 * (size_t)alloc));
+        DP_HIP(hipMalloc(&nl->wrap, sizeof(int) * (size_t)alloc));
+        DP_HIP(hipMalloc(&nl->cnt, sizeof(int) * (size_t)alloc));
+        DP_HIP(hipMalloc(&nl->nei, sizeof(int) * (size_t)alloc * capn));
+        DP_HIP(hipMalloc(&nl->shift, sizeof(int) * (size_t)alloc * capn));
+        DP_HIP(hipMalloc(&nl->force_tmp, sizeof(double) * 3 * (size_t)alloc));
+        nl->alloc_atoms = alloc;
+        nl->cap = capn;
+    }
+    nl->cap = cap > nl->cap ? cap : nl->cap;
+    if (!nl->flags) {
+        DP_HIP(hipMalloc(&nl->flags, sizeof(int) * kNumFlags));
+        DP_HIP(hipMemset(nl->flags, 0, sizeof(int) * kNumFlags));
+    }
+    if (!nl->scal) DP_HIP(hipMalloc(&nl->scal, sizeof(double) * 512));
+    nl->natoms = natoms;
+    dp_status s = ensure_ws(nl, DP_FP64);
+    if (s != DP_OK) return s;
+    *inout = nl;
+    return DP_OK;
+}
+
+dp_status read_flags(dp_nlist *nl, int *f, hipStream_t st)
+{
+    DP_HIP(hipStreamSynchronize(st));
+    DP_HIP(hipMemcpy(f, nl->flags, sizeof(int) * kNumFlags, hipMemcpyDeviceToHost));
+    return DP_OK;
+}
+
+dp_status check_build_flags(const int *f)
+{
+    if (f[kFlagBadType]) return fail(DP_ERR_UNSUPPORTED, "atom types other than 0 (one element only)");
+    if (f[kFlagCapOverflow])
+        return fail(DP_ERR_CAPACITY, "an atom has more skin candidates than the list capacity "
+                                     "(or coordinates lie more than 60 boxes away)");
+    if (f[kFlagCellOverflow]) return fail(DP_ERR_CAPACITY, "a cell holds more atoms than its capacity");
+    return DP_OK;
+}
+
+dp_status check_compute_args(const dp_model *m, const dp_nlist *nl, int natoms, const double *x, int mode,
+                             int precision)
+{
+    if (!m || !nl || !x) return fail(DP_ERR_ARG, "NULL model, list or coordinates");
+    if (natoms != nl->natoms) return fail(DP_ERR_ARG, "natoms differs from the list's");
+    if (mode != DP_COMPRESSED && mode != DP_PLAIN) return fail(DP_ERR_ARG, "unknown mode");
+    if (precision < DP_FP64 || precision > DP_MIXED_BF16) return fail(DP_ERR_ARG, "unknown precision");
+    if (mode == DP_COMPRESSED && !m->tab64) return fail(DP_ERR_STATE, "dp_tabulate has not run");
+    return DP_OK;
+}
+
+}  // namespace
+}  // namespace dp
+
+using namespace dp;
+
+extern "C" {
+
+dp_status dp_model_create(const dp_model_config *cfg, const double *params_h, size_t nparams, dp_model **out)
+{
+    if (!cfg || !params_h || !out) return fail(DP_ERR_ARG, "NULL argument");
+    const dp_model_config &c = *cfg;
+    if (c.ntypes != 1) return fail(DP_ERR_UNSUPPORTED, "ntypes must be 1");
+    if (!(c.rcut > 0) || !(c.rcut_smth >= 0) || !(c.rcut_smth < c.rcut))
+        return fail(DP_ERR_ARG, "need 0 <= rcut_smth < rcut");
+    if (c.sel < 1 || c.sel > 256) return fail(DP_ERR_UNSUPPORTED, "sel must be in [1, 256]");
+    if (c.emb[2] != kM || c.emb[1] * 2 != c.emb[2] || c.emb[0] * 2 != c.emb[1])
+        return fail(DP_ERR_UNSUPPORTED, "embedding widths must be 32, 64, 128");
+    if (c.m_lt != kMlt) return fail(DP_ERR_UNSUPPORTED, "M< must be 16");
+    if (c.fit[0] < 1 || c.fit[0] > kFitPad || c.fit[1] != c.fit[0] || c.fit[2] != c.fit[0])
+        return fail(DP_ERR_UNSUPPORTED, "fitting widths must be equal and at most 256");
+    if (!std::isfinite(c.desc_scale)) return fail(DP_ERR_ARG, "desc_scale must be finite");
+    if (c.switch_kind != 0 && c.switch_kind != 1) return fail(DP_ERR_ARG, "switch_kind must be 0 or 1");
+    if (nparams != expected_params(c)) return fail(DP_ERR_ARG, "parameter count does not match the config");
+    for (size_t i = 0; i < nparams; i++)
+        if (!std::isfinite(params_h[i])) return fail(DP_ERR_ARG, "non-finite parameter");
+
+    dp_model *m = new dp_model();
+    m->cfg = c;
+    DP_HIP(hipGetDevice(&m->device));
+    m->d1 = c.emb[0];
+    m->d2 = c.emb[1];
+    m->d3 = c.emb[2];
+    m->f1 = c.fit[0];
+    m->f2 = c.fit[1];
+    m->f3 = c.fit[2];
+    size_t nemb = (size_t)m->d1 * 2 + (size_t)m->d1 * m->d2 + m->d2 + (size_t)m->d2 * m->d3 + m->d3;
+    const double *p = params_h + nemb;
+    int F = m->f1, P = kFitPad;
+    const double *V1 = p, *c1 = V1 + (size_t)kDdim * F, *V2 = c1 + F, *c2 = V2 + (size_t)F * F, *V3 = c2 + F,
+                 *c3 = V3 + (size_t)F * F, *w4 = c3 + F, *b4 = w4 + F;
+    std::vector<double> mats[6];
+    mats[0].assign((size_t)kDdim * P, 0.0);   // V1  [2048][256]
+    mats[1].assign((size_t)P * kDdim, 0.0);   // V1t [256][2048]
+    for (int a = 0; a < kDdim; a++)
+        for (int o = 0; o < F; o++) {
+            mats[0][(size_t)a * P + o] = V1[(size_t)a * F + o];
+            mats[1][(size_t)o * kDdim + a] = V1[(size_t)a * F + o];
+        }
+    const double *Vs[2] = {V2, V3};
+    for (int k = 0; k < 2; k++) {
+        mats[2 + 2 * k].assign((size_t)P * P, 0.0);
+        mats[3 + 2 * k].assign((size_t)P * P, 0.0);
+        for (int a = 0; a < F; a++)
+            for (int o = 0; o < F; o++) {
+                mats[2 + 2 * k][(size_t)a * P + o] = Vs[k][(size_t)a * F + o];
+                mats[3 + 2 * k][(size_t)o * P + a] = Vs[k][(size_t)a * F + o];
+            }
+    }
+    std::vector<double> fb(4 * P + 1, 0.0);
+    for (int o = 0; o < F; o++) {
+        fb[o] = c1[o];
+        fb[P + o] = c2[o];
+        fb[2 * P + o] = c3[o];
+        fb[3 * P + o] = w4[o];
+    }
+    fb[4 * P] = b4[0];
+    m->b4 = b4[0];
+    std::vector<float> fbf(fb.begin(), fb.end());
+    std::vector<double> emb(params_h, params_h + nemb);
+    dp_status s;
+    if ((s = upload(&m->emb_d, emb)) != DP_OK || (s = upload(&m->fitb_d, fb)) != DP_OK ||
+        (s = upload(&m->fitb_f, fbf)) != DP_OK || (s = upload_fit(m->w64, mats, DP_FP64)) != DP_OK ||
+        (s = upload_fit(m->w32, mats, DP_FP32)) != DP_OK || (s = upload_fit(m->wbf, mats, DP_MIXED_BF16)) != DP_OK) {
+        dp_model_destroy(m);
+        return s;
+    }
+    *out = m;
+    return DP_OK;
+}
+
+dp_status dp_model_destroy(dp_model *m)
+{
+    if (!m) return DP_OK;
+    void *p[] = {m->emb_d, m->fitb_d, m->fitb_f, m->tab64, m->tab32, m->nodes};
+    for (void *q : p)
+        if (q) (void)hipFree(q);
+    free_fit(m->w64);
+    free_fit(m->w32);
+    free_fit(m->wbf);
+    delete m;
+    return DP_OK;
+}
+
+dp_status dp_tabulate(dp_model *m, double s_max, double stride, double tail_max, double tail_stride, void *stream)
+{
+    if (!m) return fail(DP_ERR_ARG, "NULL model");
+    if (!(s_max > 0) || !(stride > 0) || !(tail_max >= s_max) || !std::isfinite(tail_max))
+        return fail(DP_ERR_ARG, "need s_max > 0, stride > 0, tail_max >= s_max");
+    double nf = s_max / stride;
+    if (nf > 1e6) return fail(DP_ERR_ARG, "too many intervals");
+    int n_fine = (int)std::llround(nf);
+    if (n_fine < 1 || std::fabs(n_fine * stride - s_max) > 1e-9 * s_max)
+        return fail(DP_ERR_ARG, "s_max must be a multiple of stride");
+    int n_tail = 0;
+    if (tail_max > s_max) {
+        if (!(tail_stride > 0)) return fail(DP_ERR_ARG, "tail_stride must be > 0");
+        double nt = (tail_max - s_max) / tail_stride;
+        if (nt > 1e6) return fail(DP_ERR_ARG, "too many tail intervals");
+        n_tail = (int)std::llround(nt);
+        if (n_tail < 1 || std::fabs(n_tail * tail_stride - (tail_max - s_max)) > 1e-9 * tail_max)
+            return fail(DP_ERR_ARG, "tail_max - s_max must be a multiple of tail_stride");
+    }
+    void *p[] = {m->tab64, m->tab32, m->nodes};
+    for (void *q : p)
+        if (q) DP_HIP(hipFree(q));
+    m->tab64 = nullptr;
+    m->tab32 = nullptr;
+    m->nodes = nullptr;
+    m->tab.n_fine = n_fine;
+    m->tab.n_tail = n_tail;
+    m->tab.h = stride;
+    m->tab.s_max = s_max;
+    m->tab.h_tail = n_tail ? tail_stride : stride;
+    m->tab.tail_max = n_tail ? tail_max : s_max;
+    int n = n_fine + n_tail;
+    DP_HIP(hipMalloc(&m->tab64, sizeof(double) * (size_t)n * kM * 6));
+    DP_HIP(hipMalloc(&m->tab32, sizeof(float) * (size_t)n * kM * 8));
+    DP_HIP(hipMalloc(&m->nodes, sizeof(double) * (size_t)(n + 1) * kM * 3));
+    dp_status s = launch_tabulate(m, (hipStream_t)stream);
+    if (s != DP_OK) return s;
+    return step_check("tabulate", (hipStream_t)stream);
+}
+
+dp_status dp_table_download(dp_model *m, double *coef_h, int *n_int)
+{
+    if (!m) return fail(DP_ERR_ARG, "NULL model");
+    if (!m->tab64) return fail(DP_ERR_STATE, "dp_tabulate has not run");
+    int n = m->tab.n_int();
+    if (n_int) *n_int = n;
+    if (coef_h) {
+        DP_HIP(hipDeviceSynchronize());
+        DP_HIP(hipMemcpy(coef_h, m->tab64, sizeof(double) * (size_t)n * kM * 6, hipMemcpyDeviceToHost));
+    }
+    return DP_OK;
+}
+
+dp_status dp_build_nlist(dp_model *m, int natoms, const double *coords_d, const int *types_d,
+                         const double *box_h, double skin, dp_nlist **inout, void *stream)
+{
+    if (!m || !coords_d || !inout) return fail(DP_ERR_ARG, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    for (int attempt = 0; attempt < 4; attempt++) {
+        dp_status s = prepare_nlist(m, natoms, box_h, skin, inout);
+        if (s != DP_OK) return s;
+        dp_nlist *nl = *inout;
+        s = launch_build_nlist(m, nl, coords_d, types_d, true, st);
+        if (s != DP_OK) return s;
+        if ((s = step_check("build_nlist", st)) != DP_OK) return s;
+        int f[kNumFlags];
+        if ((s = read_flags(nl, f, st)) != DP_OK) return s;
+        if (f[kFlagCellOverflow] && !f[kFlagBadType] && attempt < 3) {
+            nl->cellcap *= 2;   // a crowded cell: retry with room to spare
+            continue;
+        }
+        return check_build_flags(f);
+    }
+    return fail(DP_ERR_CAPACITY, "cell capacity");
+}
+
+dp_status dp_nlist_destroy(dp_nlist *nl)
+{
+    if (!nl) return DP_OK;
+    free_nlist_arrays(nl);
+    delete nl;
+    return DP_OK;
+}
+
+static dp_status compute_common(dp_model *m, dp_nlist *nl, int natoms, const double *x, int mode, int precision,
+                                double *energy, double *force, double *virial, double *atom_energy, int *nnei,
+                                double *T, double *D, hipStream_t st)
+{
+    dp_status s = check_compute_args(m, nl, natoms, x, mode, precision);
+    if (s != DP_OK) return s;
+    if ((s = ensure_ws(nl, precision)) != DP_OK) return s;
+    ComputeArgs a;
+    a.m = m;
+    a.nl = nl;
+    a.natoms = natoms;
+    a.x = x;
+    a.precision = precision;
+    a.energy = energy;
+    a.virial = virial;
+    a.atom_energy = atom_energy;
+    a.nnei_out = nnei;
+    a.T_out = T;
+    a.D_out = D;
+    a.need_forces = force || virial;
+    a.force = force ? force : nl->force_tmp;
+    return mode == DP_COMPRESSED ? run_compressed(a, st) : run_plain(a, st);
+}
+
+dp_status dp_compute(dp_model *m, dp_nlist *nl, int natoms, const double *coords_d, const int *types_d,
+                     const double *box_h, int mode, int precision, double *energy_d, double *force_d,
+                     double *virial_d, double *atom_energy_d, void *stream)
+{
+    (void)types_d;
+    if (nl && nl->periodic) {
+        double L[3];
+        if (!box_h || !box_ok(box_h, L) || L[0] != nl->L[0] || L[1] != nl->L[1] || L[2] != nl->L[2])
+            return fail(DP_ERR_ARG, "box differs from the one the list was built for");
+    } else if (nl && box_h) {
+        return fail(DP_ERR_ARG, "the list was built for an open cluster");
+    }
+    return compute_common(m, nl, natoms, coords_d, mode, precision, energy_d, force_d, virial_d, atom_energy_d,
+                          nullptr, nullptr, nullptr, (hipStream_t)stream);
+}
+
+dp_status dp_descriptor(dp_model *m, dp_nlist *nl, int natoms, const double *coords_d, const double *box_h,
+                        int mode, int precision, int *nnei_d, double *T_d, double *D_d, void *stream)
+{
+    (void)box_h;
+    return compute_common(m, nl, natoms, coords_d, mode, precision, nullptr, nullptr, nullptr, nullptr, nnei_d,
+                          T_d, D_d, (hipStream_t)stream);
+}
+
+dp_status dp_nlist_stats(dp_nlist *nl, int *max_nei, int *n_sel_overflow, int *n_table_oob, int *n_cap_overflow)
+{
+    if (!nl) return fail(DP_ERR_ARG, "NULL list");
+    int f[kNumFlags];
+    DP_HIP(hipDeviceSynchronize());
+    DP_HIP(hipMemcpy(f, nl->flags, sizeof(f), hipMemcpyDeviceToHost));
+    if (max_nei) *max_nei = f[kFlagMaxNei];
+    if (n_sel_overflow) *n_sel_overflow = f[kFlagSelOverflow];
+    if (n_table_oob) *n_table_oob = f[kFlagTableOob];
+    if (n_cap_overflow) *n_cap_overflow = f[kFlagCapOverflow];
+    return DP_OK;
+}
+
+dp_status dp_nve_run(dp_model *m, dp_nlist **nlp, int natoms, double *x, double *v, const int *types,
+                     const double *box_h, double mass, double dt_fs, int nsteps, int rebuild_every, double skin,
+                     int mode, int precision, double *thermo, void *stream)
+{
+    if (!m || !nlp || !x || !v) return fail(DP_ERR_ARG, "NULL argument");
+    if (!(mass > 0) || !(dt_fs > 0) || nsteps < 0 || rebuild_every < 1)
+        return fail(DP_ERR_ARG, "need mass > 0, dt > 0, nsteps >= 0, rebuild_every >= 1");
+    hipStream_t st = (hipStream_t)stream;
+    dp_status s = prepare_nlist(m, natoms, box_h, skin, nlp);
+    if (s != DP_OK) return s;
+    dp_nlist *nl = *nlp;
+    if ((s = check_compute_args(m, nl, natoms, x, mode, precision)) != DP_OK) return s;
+    if ((s = launch_build_nlist(m, nl, x, types, true, st)) != DP_OK) return s;
+    if ((s = step_check("build_nlist", st)) != DP_OK) return s;
+    double *F = nl->force_tmp, *E = nl->scal, *part = nl->scal + 256;
+    double kick = 0.5 * dt_fs * acc_unit() / mass, kef = 0.5 * mass * ke_unit();
+    s = compute_common(m, nl, natoms, x, mode, precision, E, F, nullptr, nullptr, nullptr, nullptr, nullptr, st);
+    if (s != DP_OK) return s;
+    if (thermo) launch_thermo(v, E, natoms, kef, thermo, part, st);
+    for (int step = 1; step <= nsteps; step++) {
+        launch_verlet_kick_drift(x, v, F, natoms, kick, dt_fs, st);
+        if (step % rebuild_every == 0) {
+            DP_TIMED("nlist", st, s = launch_build_nlist(m, nl, x, types, false, st));
+            if (s != DP_OK) return s;
+            if ((s = step_check("build_nlist", st)) != DP_OK) return s;
+        }
+        s = compute_common(m, nl, natoms, x, mode, precision, E, F, nullptr, nullptr, nullptr, nullptr, nullptr, st);
+        if (s != DP_OK) return s;
+        launch_verlet_kick(v, F, natoms, kick, st);
+        if (thermo) launch_thermo(v, E, natoms, kef, thermo + 2 * step, part, st);
+        if ((s = step_check("verlet", st)) != DP_OK) return s;
+    }
+    int f[kNumFlags];
+    if ((s = read_flags(nl, f, st)) != DP_OK) return s;
+    return check_build_flags(f);
+}
+
+const char *dp_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+namespace dp {
+dp_status run_plain(const ComputeArgs &, hipStream_t) { return fail(DP_ERR_UNSUPPORTED, "plain mode not built yet"); }
+}  // namespace dp

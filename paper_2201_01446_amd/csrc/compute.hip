@@ -1,0 +1,229 @@
+// compute.hip -- one force step of the compressed model, and the
+// velocity-Verlet kernels, as sequences of launches on one stream.
+//
+// Compressed step (per configuration, all on the caller's stream):
+//   k_emb_fwd        env matrix + tabulated G fused with R^T G -> T, D
+//   3 x GEMM         fitting net forward (tanh / shortcut epilogues)
+//   k_energy         E_i, dz3
+//   3 x GEMM         fitting-net input gradient -> dD
+//   k_dT             dE/dT from dE/dD
+//   k_emb_bwd        adjoint of the fused step -> forces (atomics), W_i
+//   k_reduce_*       deterministic FP64 sums of E_i and W_i
+// Buffers live in the neighbor list's workspace; rows are padded to 64 so
+// the GEMM tiles never read past an allocation.
+
+#include "dp_internal.h"
+
+#include <type_traits>
+
+namespace dp {
+
+namespace {
+
+struct WS {
+    void *T, *D, *y1r, *y1o, *y2r, *y2o, *t2r, *t3r, *dz3o, *dy2r, *dz2o, *dz1o, *dDr, *dT;
+    double *e_atom, *w_atom, *part;
+};
+
+size_t sizes(int precision, size_t &rs, size_t &os)
+{
+    rs = precision == DP_FP64 ? 8 : 4;
+    os = precision == DP_FP64 ? 8 : (precision == DP_FP32 ? 4 : 2);
+    return 0;
+}
+
+size_t ws_bytes_for(int np, int precision)
+{
+    size_t rs, os;
+    sizes(precision, rs, os);
+    auto al = [](size_t b) { return (size_t)round_up((long)b, 256); };
+    size_t r = 0;
+    r += al(np * 4 * kM * rs);          // T
+    r += al(np * (size_t)kDdim * os);   // D
+    r += 5 * al(np * (size_t)kFitPad * rs);   // y1r y2r t2r t3r dy2r
+    r += 5 * al(np * (size_t)kFitPad * os);   // y1o y2o dz3o dz2o dz1o
+    r += al(np * (size_t)kDdim * rs);   // dD
+    r += al(np * 4 * kM * rs);          // dT
+    r += al(np * 8) + al(np * 72) + al(256 * 10 * 8);
+    return r;
+}
+
+WS carve(void *base, int np, int precision)
+{
+    size_t rs, os;
+    sizes(precision, rs, os);
+    char *p = (char *)base;
+    auto take = [&](size_t b) {
+        void *q = p;
+        p += round_up((long)b, 256);
+        return q;
+    };
+    WS w;
+    w.T = take(np * 4 * kM * rs);
+    w.D = take(np * (size_t)kDdim * os);
+    w.y1r = take(np * (size_t)kFitPad * rs);
+    w.y2r = take(np * (size_t)kFitPad * rs);
+    w.t2r = take(np * (size_t)kFitPad * rs);
+    w.t3r = take(np * (size_t)kFitPad * rs);
+    w.dy2r = take(np * (size_t)kFitPad * rs);
+    w.y1o = take(np * (size_t)kFitPad * os);
+    w.y2o = take(np * (size_t)kFitPad * os);
+    w.dz3o = take(np * (size_t)kFitPad * os);
+    w.dz2o = take(np * (size_t)kFitPad * os);
+    w.dz1o = take(np * (size_t)kFitPad * os);
+    w.dDr = take(np * (size_t)kDdim * rs);
+    w.dT = take(np * 4 * kM * rs);
+    w.e_atom = (double *)take(np * 8);
+    w.w_atom = (double *)take(np * 72);
+    w.part = (double *)take(256 * 10 * 8);
+    return w;
+}
+
+template <typename TA, typename TR>
+dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw, const TR *fb,
+                hipStream_t st)
+{
+    const dp_model *m = a.m;
+    int n = a.natoms;
+    DP_TIMED("emb_fwd", st, launch_emb_fwd(m, a.nl, n, a.x, a.precision, w.T, w.D, a.nnei_out, st));
+    dp_status s = step_check("emb_fwd", st);
+    if (s != DP_OK) return s;
+    if (a.T_out) launch_to_double<TR>((long)n * 4 * kM, (const TR *)w.T, a.T_out, st);
+    if (a.D_out) launch_to_double<TA>((long)n * kDdim, (const TA *)w.D, a.D_out, st);
+    const TR *c1 = fb, *c2 = fb + kFitPad, *c3 = fb + 2 * kFitPad, *w4 = fb + 3 * kFitPad;
+    Epi e{};
+    // forward
+    e = Epi{c1, nullptr, nullptr, nullptr, w.y1r, w.y1o, nullptr};
+    DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T1, np, kFitPad, kDdim, (const TA *)w.D, (const TA *)fw.V1t, e, st));
+    e = Epi{c2, w.y1r, nullptr, nullptr, w.y2r, w.y2o, w.t2r};
+    DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T2, np, kFitPad, kFitPad, (const TA *)w.y1o, (const TA *)fw.V2t, e, st));
+    e = Epi{c3, nullptr, nullptr, nullptr, nullptr, nullptr, w.t3r};
+    DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T3, np, kFitPad, kFitPad, (const TA *)w.y2o, (const TA *)fw.V3t, e, st));
+    launch_energy<TA, TR>(n, (const TR *)w.y2r, (const TR *)w.t3r, w4, a.m->b4, w.e_atom,
+                          a.need_forces ? (TA *)w.dz3o : nullptr, st);
+    if ((s = step_check("fitting_forward", st)) != DP_OK) return s;
+    if (a.need_forces) {
+        e = Epi{nullptr, nullptr, w4, w.t2r, w.dy2r, w.dz2o, nullptr};
+        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_BWD, np, kFitPad, kFitPad, (const TA *)w.dz3o, (const TA *)fw.V3, e, st));
+        e = Epi{nullptr, w.dy2r, nullptr, w.y1r, nullptr, w.dz1o, nullptr};
+        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_BWD, np, kFitPad, kFitPad, (const TA *)w.dz2o, (const TA *)fw.V2, e, st));
+        e = Epi{nullptr, nullptr, nullptr, nullptr, w.dDr, nullptr, nullptr};
+        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_LIN, np, kDdim, kFitPad, (const TA *)w.dz1o, (const TA *)fw.V1, e, st));
+        DP_TIMED("dT", st, launch_dT<TR>(n, (const TR *)w.dDr, (const TR *)w.T, (TR *)w.dT, st));
+        if ((s = step_check("fitting_backward", st)) != DP_OK) return s;
+        launch_fill_zero(a.force, 3L * n, st);
+        DP_TIMED("emb_bwd", st, launch_emb_bwd(m, a.nl, n, a.x, a.precision, w.dT, a.force, w.w_atom, st));
+        if ((s = step_check("emb_bwd", st)) != DP_OK) return s;
+    }
+    if (a.energy || a.virial)
+        launch_reduce(n, w.e_atom, a.need_forces ? w.w_atom : nullptr, w.part, a.energy,
+                      a.need_forces ? a.virial : nullptr, st);
+    if (a.atom_energy)
+        DP_HIP(hipMemcpyAsync(a.atom_energy, w.e_atom, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    return step_check("reduce", st);
+}
+
+}  // namespace
+
+dp_status ensure_ws(dp_nlist *nl, int precision)
+{
+    int np = (int)round_up(nl->alloc_atoms, kRowPad);
+    size_t need = ws_bytes_for(np, DP_FP64);   // the largest of the three layouts
+    (void)precision;
+    if (nl->ws_bytes >= need) return DP_OK;
+    if (nl->ws) DP_HIP(hipFree(nl->ws));
+    nl->ws = nullptr;
+    nl->ws_bytes = 0;
+    hipError_t e = hipMalloc(&nl->ws, need);
+    if (e != hipSuccess) return fail(DP_ERR_OOM, "workspace allocation failed");
+    nl->ws_bytes = need;
+    // rows past natoms are read by GEMM tiles: keep them finite (zero)
+    DP_HIP(hipMemset(nl->ws, 0, need));
+    return DP_OK;
+}
+
+dp_status run_compressed(const ComputeArgs &a, hipStream_t st)
+{
+    int np = (int)round_up(a.nl->alloc_atoms, kRowPad);
+    WS w = carve(a.nl->ws, np, a.precision);
+    if (a.precision == DP_FP64) return run_t<double, double>(a, w, np, a.m->w64, a.m->fitb_d, st);
+    if (a.precision == DP_FP32) return run_t<float, float>(a, w, np, a.m->w32, a.m->fitb_f, st);
+    return run_t<__bf16, float>(a, w, np, a.m->wbf, a.m->fitb_f, st);
+}
+
+// ---------------------------------------------------------------- Verlet
+namespace {
+
+// 1 eV/(A amu) in A/fs^2, and 1 amu A^2/fs^2 in eV.
+constexpr double kAcc = 9.64853321e-3;
+constexpr double kKe = 103.642691;
+
+__global__ void k_kick_drift(double *__restrict__ x, double *__restrict__ v, const double *__restrict__ f,
+                             long n3, double kick, double dt)
+{
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= n3) return;
+    double vi = v[i] + kick * f[i];
+    v[i] = vi;
+    x[i] += dt * vi;
+}
+
+__global__ void k_kick(double *__restrict__ v, const double *__restrict__ f, long n3, double kick)
+{
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < n3) v[i] += kick * f[i];
+}
+
+__global__ void __launch_bounds__(256) k_vv_partial(long n3, const double *__restrict__ v,
+                                                    double *__restrict__ part)
+{
+    __shared__ double sh[256];
+    long per = (n3 + gridDim.x - 1) / gridDim.x;
+    long beg = blockIdx.x * per, end = min(n3, beg + per);
+    double s = 0;
+    for (long i = beg + threadIdx.x; i < end; i += 256) s += v[i] * v[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_thermo_final(int nblk, const double *__restrict__ part, const double *__restrict__ energy,
+                               double ke_factor, double *row)
+{
+    if (threadIdx.x != 0) return;
+    double s = 0;
+    for (int b = 0; b < nblk; b++) s += part[b];
+    row[0] = *energy;
+    row[1] = ke_factor * s;
+}
+
+}  // namespace
+
+void launch_verlet_kick_drift(double *x, double *v, const double *f, int n, double kick, double dt,
+                              hipStream_t st)
+{
+    long n3 = 3L * n;
+    hipLaunchKernelGGL(k_kick_drift, dim3(div_up(n3, 256)), dim3(256), 0, st, x, v, f, n3, kick, dt);
+}
+
+void launch_verlet_kick(double *v, const double *f, int n, double kick, hipStream_t st)
+{
+    long n3 = 3L * n;
+    hipLaunchKernelGGL(k_kick, dim3(div_up(n3, 256)), dim3(256), 0, st, v, f, n3, kick);
+}
+
+void launch_thermo(const double *v, const double *energy, int n, double ke_factor, double *row, double *part,
+                   hipStream_t st)
+{
+    hipLaunchKernelGGL(k_vv_partial, dim3(256), dim3(256), 0, st, 3L * n, v, part);
+    hipLaunchKernelGGL(k_thermo_final, dim3(1), dim3(64), 0, st, 256, part, energy, ke_factor, row);
+}
+
+double acc_unit() { return kAcc; }
+double ke_unit() { return kKe; }
+
+}  // namespace dp

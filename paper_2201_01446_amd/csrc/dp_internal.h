@@ -1,0 +1,195 @@
+// dp_internal.h -- handle layouts, launch helpers and device utilities shared
+// by the HIP translation units of libdp (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/dp.h"
+
+namespace dp {
+
+// Fixed model shape of this build: M = 128 embedding columns, M< = 16.
+constexpr int kM = 128;
+constexpr int kMlt = 16;
+constexpr int kDdim = kM * kMlt;     // 2048 descriptor entries per atom
+constexpr int kFitPad = 256;         // fitting widths padded to 256 (zero columns)
+constexpr int kCapMax = 1024;        // skin candidates per atom, upper bound
+constexpr int kRowPad = 64;          // atom rows of every GEMM operand padded to 64
+
+// Device-side sticky counters of a neighbor list.
+enum Flag {
+    kFlagMaxNei = 0,       // atomicMax of neighbors within rcut
+    kFlagSelOverflow = 1,  // atoms with more than sel neighbors within rcut
+    kFlagTableOob = 2,     // table look-ups past the last node
+    kFlagCapOverflow = 3,  // atoms whose candidate list hit cap
+    kFlagCellOverflow = 4, // atoms that did not fit their cell
+    kFlagBadType = 5,      // atoms with a type other than 0
+    kNumFlags = 8
+};
+
+struct TableInfo {
+    int n_fine = 0, n_tail = 0;
+    double h = 0, s_max = 0, h_tail = 0, tail_max = 0;
+    int n_int() const { return n_fine + n_tail; }
+};
+
+// Fitting-net weights in one precision, widths padded to kFitPad.
+//   Vk  : [in][kFitPad] forward operands, Vkt : [kFitPad][in] transposed
+//   (backward operands), bias and output vector as float/double.
+struct FitWeights {
+    void *V1 = nullptr, *V2 = nullptr, *V3 = nullptr;
+    void *V1t = nullptr, *V2t = nullptr, *V3t = nullptr;
+};
+
+}  // namespace dp
+
+struct dp_model {
+    dp_model_config cfg;
+    int device = 0;
+    int d1 = 0, d2 = 0, d3 = 0, f1 = 0, f2 = 0, f3 = 0;
+    // parameters on the device
+    double *emb_d = nullptr;     // W0 b0 W1 b1 W2 b2, FP64, file layout
+    double *fitb_d = nullptr;    // c1 c2 c3 w4 (each kFitPad, zero padded) + b4, FP64
+    float *fitb_f = nullptr;     // same in FP32
+    double b4 = 0;               // output bias
+    dp::FitWeights w64, w32, wbf;   // double, float, bf16 GEMM operands
+    // table
+    dp::TableInfo tab;
+    double *tab64 = nullptr;     // [n_int][M][6]
+    float *tab32 = nullptr;      // [n_int][M][8] (coefficients 0..5, two zero pads)
+    double *nodes = nullptr;     // scratch [n_int+1][M][3] of node values g, g', g''
+};
+
+struct dp_nlist {
+    int device = 0;
+    int natoms = 0;
+    int alloc_atoms = 0;
+    int cap = 0;
+    bool periodic = false;
+    double L[3] = {0, 0, 0};
+    double rc_build = 0;
+    // cell grid
+    int nc[3] = {1, 1, 1};
+    int cellcap = 0;
+    size_t ncell_alloc = 0;
+    int *cell_cnt = nullptr;
+    int *cell_atoms = nullptr;
+    // wrapped positions and image index (int8 x3 packed) of every atom at build
+    double *wpos = nullptr;
+    int *wrap = nullptr;
+    // candidates
+    int *cnt = nullptr;      // [natoms]
+    int *nei = nullptr;      // [natoms * cap]
+    int *shift = nullptr;    // [natoms * cap], int8 x3 packed image shift
+    int *flags = nullptr;    // [kNumFlags]
+    // per-configuration scratch of dp_compute
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    void *ws_plain = nullptr;
+    size_t ws_plain_bytes = 0;
+    double *force_tmp = nullptr;   // forces when the caller wants only the virial
+    double *scal = nullptr;        // [16] device scalars (energy, partial sums)
+};
+
+namespace dp {
+
+// ----------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+dp_status fail(dp_status st, const std::string &msg);
+dp_status hip_fail(hipError_t e, const char *what);
+
+#define DP_HIP(call)                                                   \
+    do {                                                               \
+        hipError_t e_ = (call);                                        \
+        if (e_ != hipSuccess) return dp::hip_fail(e_, #call);          \
+    } while (0)
+
+// Records HIP events around the enclosed launches on `st` when timing is
+// enabled (dp_timers_enable); aggregated by name in dp_timers_read.
+class TimerScope {
+  public:
+    TimerScope(const char *name, hipStream_t st);
+    ~TimerScope();
+
+  private:
+    const char *name_;
+    hipStream_t st_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+#define DP_TIMED(name, st, ...)              \
+    do {                                     \
+        dp::TimerScope ts_(name, st);        \
+        __VA_ARGS__;                         \
+    } while (0)
+
+// After a group of launches: the launch error, if any; and, when the
+// environment sets DP_SYNC_CHECK=1, a synchronisation that attributes an
+// asynchronous kernel failure to the named step.
+dp_status step_check(const char *name, hipStream_t st);
+
+inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
+inline long round_up(long a, long b) { return (a + b - 1) / b * b; }
+
+// ------------------------------------------------------------- launchers
+// (defined in the kernel translation units; all enqueue on `st`)
+void launch_fill_zero(double *p, long n, hipStream_t st);
+void launch_fill_zero_bytes(void *p, size_t nbytes, hipStream_t st);
+void launch_fill_zero_int(int *p, long n, hipStream_t st);
+dp_status launch_tabulate(dp_model *m, hipStream_t st);
+dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, const int *types,
+                             bool reset_flags, hipStream_t st);
+
+// Epilogues of the fitting-net GEMM C = A Bt^T (see fit.hip).
+enum EpiKind { EPI_LIN = 0, EPI_T1 = 1, EPI_T2 = 2, EPI_T3 = 3, EPI_BWD = 4 };
+struct Epi {
+    const void *bias;  // TR[N]
+    const void *res;   // TR[M][N]
+    const void *resv;  // TR[N], broadcast over rows
+    const void *tt;    // TR[M][N] tanh outputs
+    void *out_r;       // TR[M][N]
+    void *out_o;       // TA[M][N]
+    void *out_t;       // TR[M][N]
+};
+template <typename TA, typename TR>
+void launch_gemm(int epi, int M, int N, int K, const TA *A, const TA *Bt, const Epi &e, hipStream_t st);
+template <typename TA, typename TR>
+void launch_energy(int n, const TR *y2, const TR *t3, const TR *w4, double b4, double *e_atom, TA *dz3,
+                   hipStream_t st);
+template <typename TR>
+void launch_dT(int n, const TR *dD, const TR *T, TR *dT, hipStream_t st);
+void launch_reduce(int n, const double *e_atom, const double *w_atom, double *part, double *energy,
+                   double *virial, hipStream_t st);
+template <typename T>
+void launch_to_double(long n, const T *a, double *b, hipStream_t st);
+void launch_emb_fwd(const dp_model *m, const dp_nlist *nl, int n, const double *x, int precision, void *T,
+                    void *D, int *nnei, hipStream_t st);
+void launch_emb_bwd(const dp_model *m, const dp_nlist *nl, int n, const double *x, int precision,
+                    const void *dT, double *force, double *w_atom, hipStream_t st);
+
+struct ComputeArgs {
+    const dp_model *m;
+    dp_nlist *nl;
+    int natoms;
+    const double *x;
+    int precision;
+    double *energy, *force, *virial, *atom_energy;   // force: never NULL when need_forces
+    int *nnei_out;
+    double *T_out, *D_out;
+    bool need_forces;
+};
+dp_status ensure_ws(dp_nlist *nl, int precision);
+dp_status run_compressed(const ComputeArgs &a, hipStream_t st);
+dp_status run_plain(const ComputeArgs &a, hipStream_t st);
+void launch_verlet_kick_drift(double *x, double *v, const double *f, int n, double kick, double dt,
+                              hipStream_t st);
+void launch_verlet_kick(double *v, const double *f, int n, double kick, hipStream_t st);
+void launch_thermo(const double *v, const double *energy, int n, double ke_factor, double *row,
+                   double *part, hipStream_t st);
+double acc_unit();
+double ke_unit();
+
+}  // namespace dp

@@ -1,0 +1,250 @@
+// nlist.hip -- neighbor list with a skin on gfx950.
+//
+// L_Rc(i) of the paper (Sec. 2.1) is built here with a buffer of `skin`
+// beyond R_c (the MD protocol of the physical-systems section uses 2 A), so
+// that the per-step kernels only filter the stored candidates by the current
+// distance.  For each atom the candidates are all (j, periodic image) within
+// rcut + skin, sorted by distance; the sort makes neighbors that fall into
+// the same table interval consecutive, which the fused kernels exploit.
+//
+// Periodic boxes: atoms are wrapped into the box and binned into a grid of
+// nc >= 1 cells per edge with edge >= (rcut + skin)/2.  An atom scans the
+// cell offsets -R..R (R <= 2) per axis; an offset that leaves the grid maps to
+// the wrapped cell and an image shift, so boxes smaller than the cut-off
+// sphere see several images of the same atom (and of the atom itself).
+// Each candidate stores j and the image shift n with r_ij = x_j - x_i + n L in
+// the caller's (unwrapped) coordinates.
+
+#include "dp_internal.h"
+
+#include <cmath>
+#include <cstdio>
+
+namespace dp {
+
+namespace {
+
+__device__ inline int pack_shift(int a, int b, int c)
+{
+    return (a & 0xFF) | ((b & 0xFF) << 8) | ((c & 0xFF) << 16);
+}
+
+// 64-bit sort key: distance (float bits; non-negative floats order like
+// unsigned integers), then atom index, then image code (5 values per axis).
+__device__ inline unsigned long long make_key(float r, int j, int code)
+{
+    return ((unsigned long long)__float_as_uint(r) << 32) |
+           ((unsigned long long)(unsigned)j << 7) | (unsigned)code;
+}
+
+__global__ void k_zero_int(int *p, long n)
+{
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// Wrap every atom into the box, record its image index and cell.
+__global__ void k_bin(int n, const double *__restrict__ x, const int *__restrict__ types,
+                      double Lx, double Ly, double Lz, int ncx, int ncy, int ncz, int cellcap,
+                      double *__restrict__ wpos, int *__restrict__ wrap, int *__restrict__ cell_cnt,
+                      int *__restrict__ cell_atoms, int *__restrict__ flags)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (types && types[i] != 0) atomicAdd(&flags[kFlagBadType], 1);
+    double L[3] = {Lx, Ly, Lz};
+    int nc[3] = {ncx, ncy, ncz};
+    int k[3], c[3];
+    for (int a = 0; a < 3; a++) {
+        double xa = x[3 * i + a];
+        double fk = floor(xa / L[a]);
+        double w = xa - fk * L[a];
+        if (w >= L[a]) { w -= L[a]; fk += 1.0; }
+        if (w < 0.0) { w += L[a]; fk -= 1.0; }
+        // image index must fit the int8 shift encoding with room to spare
+        if (fk > 60.0 || fk < -60.0) { atomicAdd(&flags[kFlagCapOverflow], 1); fk = 0.0; }
+        k[a] = (int)fk;
+        wpos[3 * i + a] = w;
+        int ci = (int)(w * nc[a] / L[a]);
+        c[a] = ci < 0 ? 0 : (ci >= nc[a] ? nc[a] - 1 : ci);
+    }
+    wrap[i] = pack_shift(k[0], k[1], k[2]);
+    int cell = (c[0] * ncy + c[1]) * ncz + c[2];
+    int slot = atomicAdd(&cell_cnt[cell], 1);
+    if (slot < cellcap) cell_atoms[(long)cell * cellcap + slot] = i;
+    else atomicAdd(&flags[kFlagCellOverflow], 1);
+}
+
+// Sorts keys[0, P) ascending (P a power of two) with one 64-wide block.
+__device__ void bitonic_sort(unsigned long long *keys, int P)
+{
+    int lane = threadIdx.x;
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = lane; t < P / 2; t += 64) {
+                int i0 = (t / j) * 2 * j + (t % j);
+                int i1 = i0 + j;
+                bool up = (i0 & k) == 0;
+                unsigned long long a = keys[i0], b = keys[i1];
+                if ((a > b) == up) {
+                    keys[i0] = b;
+                    keys[i1] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__device__ void finish_atom(int i, int cnt, int cap, unsigned long long *keys, const int *wrap,
+                            int ki_packed, int *out_cnt, int *out_nei, int *out_shift, int *flags)
+{
+    int lane = threadIdx.x;
+    if (cnt > cap) {
+        if (lane == 0) atomicAdd(&flags[kFlagCapOverflow], 1);
+        cnt = cap;
+    }
+    int P = 1;
+    while (P < cnt) P <<= 1;
+    for (int t = cnt + lane; t < P; t += 64) keys[t] = ~0ull;
+    __syncthreads();
+    bitonic_sort(keys, P);
+    int kix = (int)(signed char)(ki_packed & 0xFF), kiy = (int)(signed char)((ki_packed >> 8) & 0xFF),
+        kiz = (int)(signed char)((ki_packed >> 16) & 0xFF);
+    for (int t = lane; t < cnt; t += 64) {
+        unsigned long long key = keys[t];
+        int lo = (int)(key & 0xFFFFFFFFu);
+        int j = (int)((unsigned)lo >> 7);
+        int code = lo & 127;
+        int sx = code / 25 - 2, sy = (code / 5) % 5 - 2, sz = code % 5 - 2;
+        int kj = wrap ? wrap[j] : 0;
+        int kjx = (int)(signed char)(kj & 0xFF), kjy = (int)(signed char)((kj >> 8) & 0xFF),
+            kjz = (int)(signed char)((kj >> 16) & 0xFF);
+        out_nei[(long)i * cap + t] = j;
+        out_shift[(long)i * cap + t] = pack_shift(sx + kix - kjx, sy + kiy - kjy, sz + kiz - kjz);
+    }
+    if (lane == 0) out_cnt[i] = cnt;
+}
+
+// One 64-thread block per atom: scan the (2R+1)^3 cell offsets.
+__global__ void __launch_bounds__(64) k_candidates_cells(
+    int n, const double *__restrict__ wpos, const int *__restrict__ wrap, double Lx, double Ly,
+    double Lz, int ncx, int ncy, int ncz, int Rx, int Ry, int Rz, int cellcap,
+    const int *__restrict__ cell_cnt, const int *__restrict__ cell_atoms, double rcs2, int cap,
+    int *__restrict__ out_cnt, int *__restrict__ out_nei, int *__restrict__ out_shift,
+    int *__restrict__ flags)
+{
+    HIP_DYNAMIC_SHARED(unsigned long long, keys)
+    __shared__ int count;
+    int i = blockIdx.x;
+    int lane = threadIdx.x;
+    if (lane == 0) count = 0;
+    __syncthreads();
+    double wi0 = wpos[3 * i], wi1 = wpos[3 * i + 1], wi2 = wpos[3 * i + 2];
+    int ci0 = min((int)(wi0 * ncx / Lx), ncx - 1), ci1 = min((int)(wi1 * ncy / Ly), ncy - 1),
+        ci2 = min((int)(wi2 * ncz / Lz), ncz - 1);
+    int wx = 2 * Rx + 1, wy = 2 * Ry + 1, wz = 2 * Rz + 1;
+    int noff = wx * wy * wz;
+    for (int oc = lane; oc < noff; oc += 64) {
+        int dx = oc / (wy * wz) - Rx, dy = (oc / wz) % wy - Ry, dz = oc % wz - Rz;
+        int cx = ci0 + dx, cy = ci1 + dy, cz = ci2 + dz;
+        // floor division / modulo for negative offsets
+        int sx = (cx >= 0) ? cx / ncx : -((-cx + ncx - 1) / ncx);
+        int sy = (cy >= 0) ? cy / ncy : -((-cy + ncy - 1) / ncy);
+        int sz = (cz >= 0) ? cz / ncz : -((-cz + ncz - 1) / ncz);
+        cx -= sx * ncx;
+        cy -= sy * ncy;
+        cz -= sz * ncz;
+        int cell = (cx * ncy + cy) * ncz + cz;
+        int m = min(cell_cnt[cell], cellcap);
+        double ox = sx * Lx - wi0, oy = sy * Ly - wi1, oz = sz * Lz - wi2;
+        int code = (sx + 2) * 25 + (sy + 2) * 5 + (sz + 2);
+        for (int t = 0; t < m; t++) {
+            int j = cell_atoms[(long)cell * cellcap + t];
+            double d0 = wpos[3 * j] + ox, d1 = wpos[3 * j + 1] + oy, d2 = wpos[3 * j + 2] + oz;
+            double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+            if (r2 < rcs2 && !(j == i && sx == 0 && sy == 0 && sz == 0)) {
+                int slot = atomicAdd(&count, 1);
+                if (slot < cap) keys[slot] = make_key((float)sqrt(r2), j, code);
+            }
+        }
+    }
+    __syncthreads();
+    finish_atom(i, count, cap, keys, wrap, wrap[i], out_cnt, out_nei, out_shift, flags);
+}
+
+// Open boundary: brute force over all atoms (for clusters of modest size).
+__global__ void __launch_bounds__(64) k_candidates_open(int n, const double *__restrict__ x,
+                                                        const int *__restrict__ types, double rcs2,
+                                                        int cap, int *__restrict__ out_cnt,
+                                                        int *__restrict__ out_nei,
+                                                        int *__restrict__ out_shift,
+                                                        int *__restrict__ flags)
+{
+    HIP_DYNAMIC_SHARED(unsigned long long, keys)
+    __shared__ int count;
+    int i = blockIdx.x;
+    int lane = threadIdx.x;
+    if (lane == 0) {
+        count = 0;
+        if (types && types[i] != 0) atomicAdd(&flags[kFlagBadType], 1);
+    }
+    __syncthreads();
+    double xi0 = x[3 * i], xi1 = x[3 * i + 1], xi2 = x[3 * i + 2];
+    for (int j = lane; j < n; j += 64) {
+        if (j == i) continue;
+        double d0 = x[3 * j] - xi0, d1 = x[3 * j + 1] - xi1, d2 = x[3 * j + 2] - xi2;
+        double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+        if (r2 < rcs2) {
+            int slot = atomicAdd(&count, 1);
+            if (slot < cap) keys[slot] = make_key((float)sqrt(r2), j, 62 /* image (0,0,0) */);
+        }
+    }
+    __syncthreads();
+    finish_atom(i, count, cap, keys, nullptr, 0, out_cnt, out_nei, out_shift, flags);
+}
+
+}  // namespace
+
+void launch_fill_zero_int(int *p, long n, hipStream_t st)
+{
+    if (n > 0) hipLaunchKernelGGL(k_zero_int, dim3(div_up(n, 256)), dim3(256), 0, st, p, n);
+}
+
+dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, const int *types,
+                             bool reset_flags, hipStream_t st)
+{
+    int n = nl->natoms;
+    double rcs2 = nl->rc_build * nl->rc_build;
+    // the sort pads the candidate count up to a power of two <= that of cap
+    int cap2 = 1;
+    while (cap2 < nl->cap) cap2 <<= 1;
+    size_t lds = sizeof(unsigned long long) * cap2;
+    (void)m;
+    if (reset_flags) launch_fill_zero_int(nl->flags, kNumFlags, st);
+    if (!nl->periodic) {
+        hipLaunchKernelGGL(k_candidates_open, dim3(n), dim3(64), lds, st, n, x, types, rcs2, nl->cap,
+                           nl->cnt, nl->nei, nl->shift, nl->flags);
+        return DP_OK;
+    }
+    long ncell = (long)nl->nc[0] * nl->nc[1] * nl->nc[2];
+    launch_fill_zero_int(nl->cell_cnt, ncell, st);
+    hipLaunchKernelGGL(k_bin, dim3(div_up(n, 256)), dim3(256), 0, st, n, x, types, nl->L[0], nl->L[1],
+                       nl->L[2], nl->nc[0], nl->nc[1], nl->nc[2], nl->cellcap,
+                       nl->wpos, nl->wrap, nl->cell_cnt,
+                       nl->cell_atoms, nl->flags);
+    int R[3];
+    for (int a = 0; a < 3; a++) {
+        double c = nl->L[a] / nl->nc[a];
+        R[a] = (int)ceil(nl->rc_build / c - 1e-12);
+        if (R[a] > 2) return fail(DP_ERR_UNSUPPORTED, "box edge shorter than (rcut + skin) / 2");
+    }
+    hipLaunchKernelGGL(k_candidates_cells, dim3(n), dim3(64), lds, st, n,
+                       nl->wpos, nl->wrap, nl->L[0], nl->L[1],
+                       nl->L[2], nl->nc[0], nl->nc[1], nl->nc[2], R[0], R[1], R[2], nl->cellcap,
+                       nl->cell_cnt, nl->cell_atoms, rcs2, nl->cap, nl->cnt, nl->nei, nl->shift,
+                       nl->flags);
+    return DP_OK;
+}
+
+}  // namespace dp

@@ -1,0 +1,63 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every symbol the headers declare, and rejects bad arguments with the
+documented status before touching the device."""
+import ctypes
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names.update(re.findall(r"\b(dp_[a-z_0-9]+)\s*\(", text))
+    return names
+
+
+def test_library_exports_declared_symbols():
+    from paper_2201_01446_amd import _lib
+    names = declared_symbols()
+    assert {"dp_build_nlist", "dp_tabulate", "dp_compute"} <= names
+    for n in sorted(names):
+        assert hasattr(_lib.lib, n), n
+
+
+def test_python_binding_names_match_header():
+    from paper_2201_01446_amd import _lib
+    assert set(_lib._SIG) | {"dp_last_error"} == declared_symbols()
+
+
+def test_bad_arguments_are_rejected():
+    from paper_2201_01446_amd import _lib
+    cfg = synth.copper_model_config()
+    p = synth.model_params(cfg)
+    P = __import__("paper_2201_01446_amd")
+    with pytest.raises(P.DPError) as e:
+        P.Model(dict(cfg, sel=0), p)
+    assert e.value.status == -5
+    with pytest.raises(P.DPError) as e:
+        P.Model(cfg, p[:-1])
+    assert e.value.status == -1 and "parameter count" in str(e.value)
+    with pytest.raises(P.DPError) as e:
+        P.Model(dict(cfg, rcut_smth=9.0), p)
+    assert e.value.status == -1
+    bad = p.copy()
+    bad[7] = np.nan
+    with pytest.raises(P.DPError):
+        P.Model(cfg, bad)
+    h = ctypes.c_void_p()
+    assert _lib.lib.dp_model_create(None, None, 0, ctypes.byref(h)) == -1
+    assert b"NULL" in _lib.lib.dp_last_error()
+    assert _lib.lib.dp_tabulate(None, 0.7, 0.01, 1.5, 0.1, None) == -1
+    assert _lib.lib.dp_compute(None, None, 0, None, None, None, 0, 0, None, None, None, None, None) == -1
+    assert _lib.lib.dp_model_destroy(None) == 0
+    assert _lib.lib.dp_nlist_destroy(None) == 0
