@@ -142,6 +142,21 @@ dp_status dp_compute(dp_model *model, dp_nlist *nlist, int natoms, const double 
                      double *energy_d, double *force_d, double *virial_d,
                      double *atom_energy_d, void *stream);
 
+/* The two halves of dp_compute, for an autograd function.  dp_energy_forward
+ * computes E (and E_i) and keeps the forward's activations (T, D, fitting-net
+ * layers) in the list's scratch.  dp_energy_backward then runs only the
+ * adjoint: the fitting-net input gradient, dE/dT, and the backward of the
+ * fused step, which recomputes G and G' from the table (G is never stored).
+ * It writes F = -dE/dx and/or W.  coords_d must be the forward's coordinates.
+ * DP_ERR_STATE if no forward of the same mode and precision is kept (any other
+ * compute on the list discards it). */
+dp_status dp_energy_forward(dp_model *model, dp_nlist *nlist, int natoms, const double *coords_d,
+                            int mode, int precision, double *energy_d, double *atom_energy_d,
+                            void *stream);
+dp_status dp_energy_backward(dp_model *model, dp_nlist *nlist, int natoms, const double *coords_d,
+                             int mode, int precision, double *force_d, double *virial_d,
+                             void *stream);
+
 /* Intermediate results for testing: per atom the number of neighbors used
  * (nnei_d, int32), T = desc_scale * R^T G (T_d, natoms x 4 x M, row k of
  * the 4 environment columns) and D = (T<)^T T (D_d, natoms x M< x M), all

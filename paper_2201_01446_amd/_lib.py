@@ -46,6 +46,8 @@ _SIG = {
     "dp_nlist_destroy": [_vp],
     "dp_compute": [_vp, _vp, _i, _vp, _vp, _vp, _i, _i, _vp, _vp, _vp, _vp, _vp],
     "dp_descriptor": [_vp, _vp, _i, _vp, _vp, _i, _i, _vp, _vp, _vp, _vp],
+    "dp_energy_forward": [_vp, _vp, _i, _vp, _i, _i, _vp, _vp, _vp],
+    "dp_energy_backward": [_vp, _vp, _i, _vp, _i, _i, _vp, _vp, _vp],
     "dp_nlist_stats": [_vp, _pi, _pi, _pi, _pi],
     "dp_nve_run": [_vp, _pvp, _i, _vp, _vp, _vp, _vp, _d, _d, _i, _i, _d, _i, _i, _vp, _vp],
     "dp_timers_enable": [_i],

@@ -311,9 +311,33 @@ dp_status dp_model_create(const dp_model_config *cfg, const double *params_h, si
     m->b4 = b4[0];
     std::vector<float> fbf(fb.begin(), fb.end());
     std::vector<double> emb(params_h, params_h + nemb);
+    // embedding weights in the plain path's GEMM layouts (d1 = 32, d2 = 64, d3 = 128)
+    const double *W0 = params_h, *b0 = W0 + 32, *W1 = b0 + 32, *b1 = W1 + 32 * 64, *W2 = b1 + 64,
+                 *b2 = W2 + 64 * 128;
+    std::vector<double> eg(64 * 32 + 128 * 64 + 64 * 128 + 64 * 64 + 32 + 32 + 64 + 128, 0.0);
+    double *W1t = eg.data(), *W2t = W1t + 64 * 32, *W2c = W2t + 128 * 64, *W1p = W2c + 64 * 128,
+           *eW0 = W1p + 64 * 64, *eb0 = eW0 + 32, *eb1 = eb0 + 32, *eb2 = eb1 + 64;
+    for (int a = 0; a < 32; a++)
+        for (int o = 0; o < 64; o++) {
+            W1t[o * 32 + a] = W1[a * 64 + o];
+            W1p[a * 64 + o] = W1[a * 64 + o];
+        }
+    for (int a = 0; a < 64; a++)
+        for (int o = 0; o < 128; o++) {
+            W2t[o * 64 + a] = W2[a * 128 + o];
+            W2c[a * 128 + o] = W2[a * 128 + o];
+        }
+    for (int a = 0; a < 32; a++) {
+        eW0[a] = W0[a];
+        eb0[a] = b0[a];
+    }
+    for (int a = 0; a < 64; a++) eb1[a] = b1[a];
+    for (int a = 0; a < 128; a++) eb2[a] = b2[a];
+    std::vector<float> egf(eg.begin(), eg.end());
     dp_status s;
     if ((s = upload(&m->emb_d, emb)) != DP_OK || (s = upload(&m->fitb_d, fb)) != DP_OK ||
-        (s = upload(&m->fitb_f, fbf)) != DP_OK || (s = upload_fit(m->w64, mats, DP_FP64)) != DP_OK ||
+        (s = upload(&m->fitb_f, fbf)) != DP_OK || (s = upload((double **)&m->embg64, eg)) != DP_OK ||
+        (s = upload((float **)&m->embg32, egf)) != DP_OK || (s = upload_fit(m->w64, mats, DP_FP64)) != DP_OK ||
         (s = upload_fit(m->w32, mats, DP_FP32)) != DP_OK || (s = upload_fit(m->wbf, mats, DP_MIXED_BF16)) != DP_OK) {
         dp_model_destroy(m);
         return s;
@@ -325,7 +349,7 @@ dp_status dp_model_create(const dp_model_config *cfg, const double *params_h, si
 dp_status dp_model_destroy(dp_model *m)
 {
     if (!m) return DP_OK;
-    void *p[] = {m->emb_d, m->fitb_d, m->fitb_f, m->tab64, m->tab32, m->nodes};
+    void *p[] = {m->emb_d, m->fitb_d, m->fitb_f, m->tab64, m->tab32, m->nodes, m->embg64, m->embg32};
     for (void *q : p)
         if (q) (void)hipFree(q);
     free_fit(m->w64);
@@ -421,10 +445,12 @@ dp_status dp_nlist_destroy(dp_nlist *nl)
 
 static dp_status compute_common(dp_model *m, dp_nlist *nl, int natoms, const double *x, int mode, int precision,
                                 double *energy, double *force, double *virial, double *atom_energy, int *nnei,
-                                double *T, double *D, hipStream_t st)
+                                double *T, double *D, hipStream_t st, int phase = 0)
 {
     dp_status s = check_compute_args(m, nl, natoms, x, mode, precision);
     if (s != DP_OK) return s;
+    if (phase == 2 && nl->fwd_token != precision + 1 + 8 * mode)
+        return fail(DP_ERR_STATE, "no kept forward of this precision and mode on this list");
     if ((s = ensure_ws(nl, precision)) != DP_OK) return s;
     ComputeArgs a;
     a.m = m;
@@ -440,6 +466,9 @@ static dp_status compute_common(dp_model *m, dp_nlist *nl, int natoms, const dou
     a.D_out = D;
     a.need_forces = force || virial;
     a.force = force ? force : nl->force_tmp;
+    a.phase = phase;
+    // any forward overwrites the kept activations
+    nl->fwd_token = phase == 1 ? precision + 1 + 8 * mode : (phase == 2 ? nl->fwd_token : 0);
     return mode == DP_COMPRESSED ? run_compressed(a, st) : run_plain(a, st);
 }
 
@@ -457,6 +486,21 @@ dp_status dp_compute(dp_model *m, dp_nlist *nl, int natoms, const double *coords
     }
     return compute_common(m, nl, natoms, coords_d, mode, precision, energy_d, force_d, virial_d, atom_energy_d,
                           nullptr, nullptr, nullptr, (hipStream_t)stream);
+}
+
+dp_status dp_energy_forward(dp_model *m, dp_nlist *nl, int natoms, const double *coords_d, int mode,
+                            int precision, double *energy_d, double *atom_energy_d, void *stream)
+{
+    return compute_common(m, nl, natoms, coords_d, mode, precision, energy_d, nullptr, nullptr, atom_energy_d,
+                          nullptr, nullptr, nullptr, (hipStream_t)stream, 1);
+}
+
+dp_status dp_energy_backward(dp_model *m, dp_nlist *nl, int natoms, const double *coords_d, int mode,
+                             int precision, double *force_d, double *virial_d, void *stream)
+{
+    if (!force_d && !virial_d) return fail(DP_ERR_ARG, "nothing to compute");
+    return compute_common(m, nl, natoms, coords_d, mode, precision, nullptr, force_d, virial_d, nullptr, nullptr,
+                          nullptr, nullptr, (hipStream_t)stream, 2);
 }
 
 dp_status dp_descriptor(dp_model *m, dp_nlist *nl, int natoms, const double *coords_d, const double *box_h,
@@ -521,6 +565,3 @@ const char *dp_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"
 
-namespace dp {
-dp_status run_plain(const ComputeArgs &, hipStream_t) { return fail(DP_ERR_UNSUPPORTED, "plain mode not built yet"); }
-}  // namespace dp

@@ -79,30 +79,37 @@ WS carve(void *base, int np, int precision)
     return w;
 }
 
-template <typename TA, typename TR>
+template <typename TA, typename TR, bool PLAIN>
 dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw, const TR *fb,
                 hipStream_t st)
 {
     const dp_model *m = a.m;
     int n = a.natoms;
-    DP_TIMED("emb_fwd", st, launch_emb_fwd(m, a.nl, n, a.x, a.precision, w.T, w.D, a.nnei_out, st));
-    dp_status s = step_check("emb_fwd", st);
-    if (s != DP_OK) return s;
-    if (a.T_out) launch_to_double<TR>((long)n * 4 * kM, (const TR *)w.T, a.T_out, st);
-    if (a.D_out) launch_to_double<TA>((long)n * kDdim, (const TA *)w.D, a.D_out, st);
+    dp_status s = DP_OK;
     const TR *c1 = fb, *c2 = fb + kFitPad, *c3 = fb + 2 * kFitPad, *w4 = fb + 3 * kFitPad;
     Epi e{};
-    // forward
-    e = Epi{c1, nullptr, nullptr, nullptr, w.y1r, w.y1o, nullptr};
-    DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T1, np, kFitPad, kDdim, (const TA *)w.D, (const TA *)fw.V1t, e, st));
-    e = Epi{c2, w.y1r, nullptr, nullptr, w.y2r, w.y2o, w.t2r};
-    DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T2, np, kFitPad, kFitPad, (const TA *)w.y1o, (const TA *)fw.V2t, e, st));
-    e = Epi{c3, nullptr, nullptr, nullptr, nullptr, nullptr, w.t3r};
-    DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T3, np, kFitPad, kFitPad, (const TA *)w.y2o, (const TA *)fw.V3t, e, st));
+    bool fwd = a.phase != 2, bwd = a.need_forces && a.phase != 1;
+    if (fwd) {
+        if (PLAIN) {
+            if ((s = plain_forward<TR, TA>(m, a.nl, n, a.x, w.T, w.D, a.nnei_out, st)) != DP_OK) return s;
+        } else {
+            DP_TIMED("emb_fwd", st, launch_emb_fwd(m, a.nl, n, a.x, a.precision, w.T, w.D, a.nnei_out, st));
+            if ((s = step_check("emb_fwd", st)) != DP_OK) return s;
+        }
+        if (a.T_out) launch_to_double<TR>((long)n * 4 * kM, (const TR *)w.T, a.T_out, st);
+        if (a.D_out) launch_to_double<TA>((long)n * kDdim, (const TA *)w.D, a.D_out, st);
+        e = Epi{c1, nullptr, nullptr, nullptr, w.y1r, w.y1o, nullptr};
+        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T1, np, kFitPad, kDdim, (const TA *)w.D, (const TA *)fw.V1t, e, st));
+        e = Epi{c2, w.y1r, nullptr, nullptr, w.y2r, w.y2o, w.t2r};
+        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T2, np, kFitPad, kFitPad, (const TA *)w.y1o, (const TA *)fw.V2t, e, st));
+        e = Epi{c3, nullptr, nullptr, nullptr, nullptr, nullptr, w.t3r};
+        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T3, np, kFitPad, kFitPad, (const TA *)w.y2o, (const TA *)fw.V3t, e, st));
+    }
+    // E_i always; dz3 = w4 (1 - t3^2) when the backward follows
     launch_energy<TA, TR>(n, (const TR *)w.y2r, (const TR *)w.t3r, w4, a.m->b4, w.e_atom,
-                          a.need_forces ? (TA *)w.dz3o : nullptr, st);
+                          bwd ? (TA *)w.dz3o : nullptr, st);
     if ((s = step_check("fitting_forward", st)) != DP_OK) return s;
-    if (a.need_forces) {
+    if (bwd) {
         e = Epi{nullptr, nullptr, w4, w.t2r, w.dy2r, w.dz2o, nullptr};
         DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_BWD, np, kFitPad, kFitPad, (const TA *)w.dz3o, (const TA *)fw.V3, e, st));
         e = Epi{nullptr, w.dy2r, nullptr, w.y1r, nullptr, w.dz1o, nullptr};
@@ -111,14 +118,18 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
         DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_LIN, np, kDdim, kFitPad, (const TA *)w.dz1o, (const TA *)fw.V1, e, st));
         DP_TIMED("dT", st, launch_dT<TR>(n, (const TR *)w.dDr, (const TR *)w.T, (TR *)w.dT, st));
         if ((s = step_check("fitting_backward", st)) != DP_OK) return s;
-        launch_fill_zero(a.force, 3L * n, st);
-        DP_TIMED("emb_bwd", st, launch_emb_bwd(m, a.nl, n, a.x, a.precision, w.dT, a.force, w.w_atom, st));
-        if ((s = step_check("emb_bwd", st)) != DP_OK) return s;
+        if (PLAIN) {
+            if ((s = plain_backward<TR>(m, a.nl, n, w.dT, a.force, w.w_atom, st)) != DP_OK) return s;
+        } else {
+            launch_fill_zero(a.force, 3L * n, st);
+            DP_TIMED("emb_bwd", st, launch_emb_bwd(m, a.nl, n, a.x, a.precision, w.dT, a.force, w.w_atom, st));
+            if ((s = step_check("emb_bwd", st)) != DP_OK) return s;
+        }
     }
-    if (a.energy || a.virial)
-        launch_reduce(n, w.e_atom, a.need_forces ? w.w_atom : nullptr, w.part, a.energy,
-                      a.need_forces ? a.virial : nullptr, st);
-    if (a.atom_energy)
+    double *energy = a.phase == 2 ? nullptr : a.energy;
+    double *virial = bwd ? a.virial : nullptr;
+    if (energy || virial) launch_reduce(n, w.e_atom, bwd ? w.w_atom : nullptr, w.part, energy, virial, st);
+    if (a.atom_energy && a.phase != 2)
         DP_HIP(hipMemcpyAsync(a.atom_energy, w.e_atom, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     return step_check("reduce", st);
 }
@@ -146,9 +157,18 @@ dp_status run_compressed(const ComputeArgs &a, hipStream_t st)
 {
     int np = (int)round_up(a.nl->alloc_atoms, kRowPad);
     WS w = carve(a.nl->ws, np, a.precision);
-    if (a.precision == DP_FP64) return run_t<double, double>(a, w, np, a.m->w64, a.m->fitb_d, st);
-    if (a.precision == DP_FP32) return run_t<float, float>(a, w, np, a.m->w32, a.m->fitb_f, st);
-    return run_t<__bf16, float>(a, w, np, a.m->wbf, a.m->fitb_f, st);
+    if (a.precision == DP_FP64) return run_t<double, double, false>(a, w, np, a.m->w64, a.m->fitb_d, st);
+    if (a.precision == DP_FP32) return run_t<float, float, false>(a, w, np, a.m->w32, a.m->fitb_f, st);
+    return run_t<__bf16, float, false>(a, w, np, a.m->wbf, a.m->fitb_f, st);
+}
+
+dp_status run_plain(const ComputeArgs &a, hipStream_t st)
+{
+    int np = (int)round_up(a.nl->alloc_atoms, kRowPad);
+    WS w = carve(a.nl->ws, np, a.precision);
+    if (a.precision == DP_FP64) return run_t<double, double, true>(a, w, np, a.m->w64, a.m->fitb_d, st);
+    if (a.precision == DP_FP32) return run_t<float, float, true>(a, w, np, a.m->w32, a.m->fitb_f, st);
+    return run_t<__bf16, float, true>(a, w, np, a.m->wbf, a.m->fitb_f, st);
 }
 
 // ---------------------------------------------------------------- Verlet

@@ -57,6 +57,8 @@ struct dp_model {
     float *fitb_f = nullptr;     // same in FP32
     double b4 = 0;               // output bias
     dp::FitWeights w64, w32, wbf;   // double, float, bf16 GEMM operands
+    void *embg64 = nullptr;      // embedding weights in GEMM layouts (plain path), FP64
+    void *embg32 = nullptr;      // the same in FP32
     // table
     dp::TableInfo tab;
     double *tab64 = nullptr;     // [n_int][M][6]
@@ -92,6 +94,7 @@ struct dp_nlist {
     void *ws_plain = nullptr;
     size_t ws_plain_bytes = 0;
     double *force_tmp = nullptr;   // forces when the caller wants only the virial
+    int fwd_token = 0;             // precision+1 while a forward's activations are kept
     double *scal = nullptr;        // [16] device scalars (energy, partial sums)
 };
 
@@ -144,7 +147,17 @@ dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, c
                              bool reset_flags, hipStream_t st);
 
 // Epilogues of the fitting-net GEMM C = A Bt^T (see fit.hip).
-enum EpiKind { EPI_LIN = 0, EPI_T1 = 1, EPI_T2 = 2, EPI_T3 = 3, EPI_BWD = 4 };
+//   EPI_LIN  out_r = acc
+//   EPI_T1   out_r = out_o = tanh(acc + bias)
+//   EPI_T2   t = tanh(acc + bias); out_t = t; out_r = out_o = res + t
+//   EPI_T3   out_t = tanh(acc + bias)
+//   EPI_BWD  dy = (resv or res) + acc; out_r = dy; out_o = dy (1 - tt^2)
+//   EPI_EMB  t = tanh(acc + bias); out_t = t; out_r = res[m][n mod resw] + t
+//            (the (x, x) shortcut of an embedding layer)
+//   EPI_FOLD columns n < half only: dy = res[m][n] + res[m][n + half] + acc;
+//            out_o[m][n] = dy (1 - tt[m][n]^2), with row pitch `half` for tt
+//            and out_o, 2 half for res (adjoint of the (x, x) shortcut)
+enum EpiKind { EPI_LIN = 0, EPI_T1 = 1, EPI_T2 = 2, EPI_T3 = 3, EPI_BWD = 4, EPI_EMB = 5, EPI_FOLD = 6 };
 struct Epi {
     const void *bias;  // TR[N]
     const void *res;   // TR[M][N]
@@ -153,6 +166,8 @@ struct Epi {
     void *out_r;       // TR[M][N]
     void *out_o;       // TA[M][N]
     void *out_t;       // TR[M][N]
+    int resw = 0;      // EPI_EMB: width of the residual input
+    int half = 0;      // EPI_FOLD
 };
 template <typename TA, typename TR>
 void launch_gemm(int epi, int M, int N, int K, const TA *A, const TA *Bt, const Epi &e, hipStream_t st);
@@ -180,7 +195,14 @@ struct ComputeArgs {
     int *nnei_out;
     double *T_out, *D_out;
     bool need_forces;
+    int phase;   // 0: whole step; 1: forward only, activations kept; 2: backward from kept activations
 };
+template <typename real, typename TD>
+dp_status plain_forward(const dp_model *m, dp_nlist *nl, int n, const double *x, void *T, void *D, int *nnei,
+                        hipStream_t st);
+template <typename real>
+dp_status plain_backward(const dp_model *m, dp_nlist *nl, int n, const void *dT, double *force, double *w_atom,
+                         hipStream_t st);
 dp_status ensure_ws(dp_nlist *nl, int precision);
 dp_status run_compressed(const ComputeArgs &a, hipStream_t st);
 dp_status run_plain(const ComputeArgs &a, hipStream_t st);

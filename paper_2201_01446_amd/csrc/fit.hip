@@ -146,13 +146,16 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const TA *
     }
     (void)VEC;
 
-    // epilogue: acc[a][b][i] is C[row][col], row = wr*32 + a*16 + 4q + i,
-    // col = wc*32 + b*16 + m
+    // epilogue: acc[a][b][i] is C[row][col] with col = wc*32 + b*16 + m and
+    // row = wr*32 + a*16 + r, where r = 4q + i for the FP32-accumulating
+    // instructions and r = 4i + q for v_mfma_f64_16x16x4f64 (lane layouts
+    // measured on gfx950)
     const TR *bias = (const TR *)e.bias;
+    constexpr bool kF64 = std::is_same<TA, double>::value;
     for (int a = 0; a < 2; a++)
         for (int b = 0; b < 2; b++)
             for (int i = 0; i < 4; i++) {
-                int gm = row0 + wr * 32 + a * 16 + 4 * q + i;
+                int gm = row0 + wr * 32 + a * 16 + (kF64 ? 4 * i + q : 4 * q + i);
                 int gn = col0 + wc * 32 + b * 16 + m;
                 if (gm >= M) continue;
                 long idx = (long)gm * N + gn;
@@ -171,6 +174,18 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const TA *
                     if (e.out_o) ((TA *)e.out_o)[idx] = tod<TA>((double)y);
                 } else if constexpr (EPI == EPI_T3) {
                     ((TR *)e.out_t)[idx] = tanh_r(v + bias[gn]);
+                } else if constexpr (EPI == EPI_EMB) {
+                    TR t = tanh_r(v + bias[gn]);
+                    ((TR *)e.out_t)[idx] = t;
+                    ((TR *)e.out_r)[idx] = ((const TR *)e.res)[(long)gm * e.resw + gn % e.resw] + t;
+                } else if constexpr (EPI == EPI_FOLD) {
+                    if (gn < e.half) {
+                        const TR *res = (const TR *)e.res;
+                        long r0 = (long)gm * 2 * e.half + gn, o = (long)gm * e.half + gn;
+                        TR dy = res[r0] + res[r0 + e.half] + v;
+                        TR t = ((const TR *)e.tt)[o];
+                        ((TA *)e.out_o)[o] = tod<TA>((double)(dy * ((TR)1 - t * t)));
+                    }
                 } else {
                     TR dy = (e.resv ? ((const TR *)e.resv)[gn] : ((const TR *)e.res)[idx]) + v;
                     if (e.out_r) ((TR *)e.out_r)[idx] = dy;
@@ -302,6 +317,8 @@ void launch_gemm(int epi, int M, int N, int K, const TA *A, const TA *Bt, const 
     case EPI_T1: hipLaunchKernelGGL((k_gemm_nt<TA, TR, EPI_T1>), grid, dim3(256), 0, st, M, N, K, A, Bt, e); break;
     case EPI_T2: hipLaunchKernelGGL((k_gemm_nt<TA, TR, EPI_T2>), grid, dim3(256), 0, st, M, N, K, A, Bt, e); break;
     case EPI_T3: hipLaunchKernelGGL((k_gemm_nt<TA, TR, EPI_T3>), grid, dim3(256), 0, st, M, N, K, A, Bt, e); break;
+    case EPI_EMB: hipLaunchKernelGGL((k_gemm_nt<TA, TR, EPI_EMB>), grid, dim3(256), 0, st, M, N, K, A, Bt, e); break;
+    case EPI_FOLD: hipLaunchKernelGGL((k_gemm_nt<TA, TR, EPI_FOLD>), grid, dim3(256), 0, st, M, N, K, A, Bt, e); break;
     default: hipLaunchKernelGGL((k_gemm_nt<TA, TR, EPI_BWD>), grid, dim3(256), 0, st, M, N, K, A, Bt, e); break;
     }
 }

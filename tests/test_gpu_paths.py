@@ -1,0 +1,161 @@
+"""The plain (untabulated) GPU path, the autograd function, and the NVE
+driver in FP32, against the oracle, through the C-ABI."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+S_MAX, H, TAIL, H_TAIL = 0.7, 0.01, 1.5, 0.1
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2201_01446_amd as P
+    assert torch.cuda.is_available()
+    return P
+
+
+@pytest.fixture(scope="module")
+def model(P, cu_cfg, cu_params):
+    m = P.Model(cu_cfg, cu_params).tabulate(S_MAX, H, TAIL, H_TAIL)
+    torch.cuda.synchronize()
+    return m
+
+
+def dev(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def run(P, model, x, box, precision, mode):
+    xd = dev(x)
+    nl = P.NeighborList(model, xd, box, skin=2.0)
+    out = P.compute(model, nl, xd, mode=mode, precision=precision, atom_energy=True)
+    torch.cuda.synchronize()
+    return {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+
+
+# ------------------------------------------------------------ plain path
+
+@pytest.mark.parametrize("ncell,sigma,seed", [(2, 0.1, 3), (5, 0.05, 11)])
+def test_plain_fp64_vs_untabulated_oracle(P, model, cu_cfg, cu_params, ncell, sigma, seed):
+    """The plain path evaluates the net itself: same result as the oracle's
+    untabulated definition up to rounding."""
+    x, box = synth.copper(ncell, sigma, seed)
+    ref = oracle.evaluate(cu_cfg, cu_params, x, box)
+    got = run(P, model, x, box, 0, 1)
+    print(f"plain fp64 {len(x)}: max dEi {np.max(np.abs(got['e_atom'] - ref['e_atom'])):.3g} "
+          f"max dF {np.max(np.abs(got['F'] - ref['F'])):.3g}")
+    assert np.max(np.abs(got["e_atom"] - ref["e_atom"])) <= 1e-10 * np.max(np.abs(ref["e_atom"]))
+    assert np.max(np.abs(got["F"] - ref["F"])) <= 1e-10 * np.max(np.abs(ref["F"]))
+    assert np.max(np.abs(got["W"] - ref["W"])) <= 1e-10 * np.max(np.abs(ref["W"]))
+
+
+def test_plain_fp32_vs_oracle(P, model, cu_cfg, cu_params):
+    x, box = synth.copper(5, 0.05, synth.SEED_CFG[1])
+    ref = oracle.evaluate(cu_cfg, cu_params, x, box)
+    got = run(P, model, x, box, 1, 1)
+    Fs = np.sqrt(np.mean(ref["F"] ** 2))
+    eF = np.sqrt(np.mean((got["F"] - ref["F"]) ** 2))
+    print(f"plain fp32: dE/N {abs(got['E'][0] - ref['E']) / len(x):.3g} RMSE_F {eF:.3g} (F_rms {Fs:.3g})")
+    assert abs(got["E"][0] - ref["E"]) / len(x) <= 1e-5
+    assert eF <= 1e-4 * Fs
+
+
+def test_plain_and_compressed_agree(P, model):
+    """At stride 0.01 the compressed and the plain paths agree to the table error."""
+    x, box = synth.copper(3, 0.1, 5)
+    a = run(P, model, x, box, 0, 0)
+    b = run(P, model, x, box, 0, 1)
+    assert abs(a["E"][0] - b["E"][0]) / len(x) < 1e-10
+    assert np.max(np.abs(a["F"] - b["F"])) < 1e-10
+
+
+# --------------------------------------------------------------- autograd
+
+def test_autograd_matches_forces_and_fd(P, model, cu_cfg, cu_params):
+    """dE/dx from the autograd function equals -F, the oracle's gradient and
+    central differences of the GPU energy (h = 1e-4 A, FP64), on 32- and
+    108-atom cells."""
+    from paper_2201_01446_amd.autograd import DPEnergy
+    tab = oracle.Table(cu_cfg, cu_params, S_MAX, H, TAIL, H_TAIL)
+    for ncell in (2, 3):
+        x, box = synth.copper(ncell, 0.1, 60 + ncell)
+        xd = dev(x).requires_grad_(True)
+        nl = P.NeighborList(model, xd.detach(), box)
+        E = DPEnergy.apply(xd, model, nl, P.FP64, P.COMPRESSED)
+        (g,) = torch.autograd.grad(E.sum(), xd)
+        g = g.cpu().numpy()
+        ref = oracle.evaluate(cu_cfg, cu_params, x, box, table=tab)
+        np.testing.assert_allclose(g, -ref["F"], rtol=0, atol=1e-10 * np.max(np.abs(ref["F"])))
+        np.testing.assert_allclose(nl.last_virial.cpu().numpy(), ref["W"], rtol=0,
+                                   atol=1e-10 * np.max(np.abs(ref["W"])))
+        h = 1e-4
+        for i, c in ((1, 0), (len(x) - 1, 2)):
+            xp, xm = x.copy(), x.copy()
+            xp[i, c] += h
+            xm[i, c] -= h
+            Ep = DPEnergy.apply(dev(xp), model, nl, P.FP64, P.COMPRESSED).item()
+            Em = DPEnergy.apply(dev(xm), model, nl, P.FP64, P.COMPRESSED).item()
+            fd = (Ep - Em) / (2 * h)
+            assert abs(g[i, c] - fd) <= 2e-9 + 1e-5 * abs(fd)
+
+
+def test_autograd_scales_grad_output_and_backward_needs_forward(P, model):
+    from paper_2201_01446_amd.autograd import DPEnergy
+    from paper_2201_01446_amd._lib import lib
+    x, box = synth.copper(2, 0.1, 9)
+    xd = dev(x).requires_grad_(True)
+    nl = P.NeighborList(model, xd.detach(), box)
+    E = DPEnergy.apply(xd, model, nl, P.FP64, P.COMPRESSED)
+    (g1,) = torch.autograd.grad(3.0 * E.sum(), xd)
+    F = P.compute(model, nl, dev(x), precision=P.FP64)["F"]
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(g1.cpu().numpy(), -3.0 * F.cpu().numpy(), rtol=1e-12, atol=1e-18)
+    # a full compute discarded the kept forward: the backward alone must refuse
+    import ctypes
+    Fd = torch.empty_like(F)
+    st = lib.dp_energy_backward(model.h, nl.h, len(x), ctypes.c_void_p(xd.detach().data_ptr()), 0, 0,
+                                ctypes.c_void_p(Fd.data_ptr()), None, None)
+    assert st == -6
+
+
+def test_autograd_500k_fp32_sampled(P, model, cu_cfg, cu_params):
+    """500,000-atom copper (50^3 cells, sigma 0.1 A) in FP32: the gradient at
+    sampled atoms against the oracle's forces there."""
+    from paper_2201_01446_amd.autograd import DPEnergy
+    x, box = synth.copper(50, 0.1, synth.SEED_CFG[4])
+    xd = dev(x).requires_grad_(True)
+    nl = P.NeighborList(model, xd.detach(), box)
+    E = DPEnergy.apply(xd, model, nl, P.FP32, P.COMPRESSED)
+    (g,) = torch.autograd.grad(E.sum(), xd)
+    g = g.cpu().numpy()
+    tab = oracle.Table(cu_cfg, cu_params, S_MAX, H, TAIL, H_TAIL)
+    rng = np.random.default_rng(4)
+    for k in rng.choice(len(x), 3, replace=False):
+        j, _, _, _ = oracle.neighbors(cu_cfg, x, box, int(k))
+        cen = np.unique(np.concatenate([[k], j])).astype(np.int32)
+        Fk = oracle.evaluate(cu_cfg, cu_params, x, box, table=tab, centers=cen)["F"][k]
+        print(f"500k atom {k}: grad {g[k]} oracle -F {-Fk}")
+        assert np.max(np.abs(g[k] + Fk)) <= 1e-4 * np.max(np.abs(Fk)) + 1e-9
+
+
+# -------------------------------------------------------------------- NVE
+
+def test_nve_fp32_energy_conservation(P, cu_cfg):
+    """FP32 forces, FP64 integration and reductions: total energy stays
+    within 1e-4 of the kinetic energy over 50 steps (forces of copper's size)."""
+    p = synth.model_params(cu_cfg)
+    synth.split_params(cu_cfg, p)["w4"][:] *= 2000.0
+    m = P.Model(cu_cfg, p).tabulate(S_MAX, H, TAIL, H_TAIL)
+    x0, box = synth.copper(4, 0.05, 3)
+    v0 = synth.maxwell_boltzmann(len(x0), 330.0, seed=4)
+    x, v = dev(x0), dev(v0)
+    nl = P.NeighborList(m, x, box)
+    th = P.nve_run(m, nl, x, v, box, synth.M_CU, 1.0, 50, rebuild_every=10, precision=P.FP32).cpu().numpy()
+    et = th.sum(1)
+    print(f"nve fp32: max |E - E0| {np.max(np.abs(et - et[0])):.3g} eV, KE0 {th[0, 1]:.3g} eV")
+    assert np.max(np.abs(et - et[0])) < 1e-3 * th[0, 1]
