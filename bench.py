@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--plain-steps", type=int, default=10)
     return ap.parse_args()
 
 
@@ -92,6 +94,13 @@ def main():
 
     res32 = run_nve(P, model, x0, v0, box, K, W, P.FP32)
     res64 = None if args.no_fp64 else run_nve(P, model, x0, v0, box, K, W, P.FP64)
+    resbf = run_nve(P, model, x0, v0, box, K, W, P.MIXED_BF16)
+    # the plain (untabulated, padded, materialised) path: same MD protocol,
+    # fewer steps (it is the denominator of the speed-up)
+    Kp = max(1, min(K, args.plain_steps))
+    plain32 = None if args.no_plain else run_nve(P, model, x0, v0, box, Kp, 1, P.FP32, mode=P.PLAIN)
+    plain64 = None if (args.no_plain or args.no_fp64) else run_nve(P, model, x0, v0, box, Kp, 1, P.FP64,
+                                                                    mode=P.PLAIN)
 
     # neighbor statistics of the final configuration (for the FLOP counts)
     d = P.descriptor(model, res32["nl"], res32["x"], precision=P.FP32)
@@ -157,6 +166,17 @@ def main():
         _, roof64, per64 = roofline(res64, "f64")
         out["fp64"] = {"value": round(v64, 1), "ms_per_step": round(res64["ms"] / K, 4),
                        "roofline": roof64, "kernels": {k: round(v["avg_ms"], 4) for k, v in per64.items()}}
+    vbf = N * K / (resbf["ms"] * 1e-3)
+    out["mixed_bf16"] = {"value": round(vbf, 1), "ms_per_step": round(resbf["ms"] / K, 4),
+                         "kernels": {k: round(v[0] / max(v[1], 1), 4) for k, v in resbf["kernels"].items()}}
+    for name, res, comp in (("plain_fp32", plain32, value), ("plain_fp64", plain64,
+                                                             out.get("fp64", {}).get("value"))):
+        if res is None:
+            continue
+        vp = N * Kp / (res["ms"] * 1e-3)
+        out[name] = {"value": round(vp, 1), "ms_per_step": round(res["ms"] / Kp, 4), "steps": Kp,
+                     "kernels": {k: round(v[0] / max(v[1], 1), 4) for k, v in res["kernels"].items()},
+                     "speedup_compressed_vs_plain": round(comp / vp, 3) if comp else None}
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out))

@@ -67,6 +67,9 @@ dp_status upload_fit(FitWeights &w, const std::vector<double> *mats, int prec)
 {
     // mats: V1 [2048][256], V1t [256][2048], V2, V2t, V3, V3t [256][256]
     void **dst[6] = {&w.V1, &w.V1t, &w.V2, &w.V2t, &w.V3, &w.V3t};
+    // K (row length) of each matrix as a GEMM Bt operand
+    const size_t kcols[6] = {(size_t)kFitPad, (size_t)kDdim, (size_t)kFitPad, (size_t)kFitPad, (size_t)kFitPad,
+                             (size_t)kFitPad};
     for (int k = 0; k < 6; k++) {
         const std::vector<double> &m = mats[k];
         size_t n = m.size();
@@ -79,10 +82,23 @@ dp_status upload_fit(FitWeights &w, const std::vector<double> *mats, int prec)
             DP_HIP(hipMalloc(dst[k], n * 4));
             DP_HIP(hipMemcpy(*dst[k], f.data(), n * 4, hipMemcpyHostToDevice));
         } else {
-            std::vector<uint16_t> b(n);
-            for (size_t i = 0; i < n; i++) b[i] = bf16_bits((float)m[i]);
-            DP_HIP(hipMalloc(dst[k], n * 2));
-            DP_HIP(hipMemcpy(*dst[k], b.data(), n * 2, hipMemcpyHostToDevice));
+            // rows of Bt as [hi | lo | hi] along K (see kSplitBf16)
+            size_t K = kcols[k], rows = n / K;
+            std::vector<uint16_t> b(3 * n);
+            for (size_t r = 0; r < rows; r++)
+                for (size_t c = 0; c < K; c++) {
+                    float f = (float)m[r * K + c];
+                    uint16_t hi = bf16_bits(f);
+                    uint32_t hb = (uint32_t)hi << 16;
+                    float hf;
+                    std::memcpy(&hf, &hb, 4);
+                    uint16_t lo = bf16_bits(f - hf);
+                    b[r * 3 * K + c] = hi;
+                    b[r * 3 * K + K + c] = lo;
+                    b[r * 3 * K + 2 * K + c] = hi;
+                }
+            DP_HIP(hipMalloc(dst[k], 3 * n * 2));
+            DP_HIP(hipMemcpy(*dst[k], b.data(), 3 * n * 2, hipMemcpyHostToDevice));
         }
     }
     return DP_OK;

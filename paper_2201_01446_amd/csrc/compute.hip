@@ -36,6 +36,7 @@ size_t ws_bytes_for(int np, int precision)
 {
     size_t rs, os;
     sizes(precision, rs, os);
+    os *= k_split(precision);
     auto al = [](size_t b) { return (size_t)round_up((long)b, 256); };
     size_t r = 0;
     r += al(np * 4 * kM * rs);          // T
@@ -52,6 +53,7 @@ WS carve(void *base, int np, int precision)
 {
     size_t rs, os;
     sizes(precision, rs, os);
+    os *= k_split(precision);
     char *p = (char *)base;
     auto take = [&](size_t b) {
         void *q = p;
@@ -88,6 +90,7 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
     dp_status s = DP_OK;
     const TR *c1 = fb, *c2 = fb + kFitPad, *c3 = fb + 2 * kFitPad, *w4 = fb + 3 * kFitPad;
     Epi e{};
+    const int ks = k_split(a.precision);   // operand K multiplier (BF16 split)
     bool fwd = a.phase != 2, bwd = a.need_forces && a.phase != 1;
     if (fwd) {
         if (PLAIN) {
@@ -97,13 +100,13 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
             if ((s = step_check("emb_fwd", st)) != DP_OK) return s;
         }
         if (a.T_out) launch_to_double<TR>((long)n * 4 * kM, (const TR *)w.T, a.T_out, st);
-        if (a.D_out) launch_to_double<TA>((long)n * kDdim, (const TA *)w.D, a.D_out, st);
+        if (a.D_out) launch_op_to_double<TA>(n, kDdim, (const TA *)w.D, a.D_out, st);
         e = Epi{c1, nullptr, nullptr, nullptr, w.y1r, w.y1o, nullptr};
-        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T1, np, kFitPad, kDdim, (const TA *)w.D, (const TA *)fw.V1t, e, st));
+        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T1, np, kFitPad, ks * kDdim, (const TA *)w.D, (const TA *)fw.V1t, e, st));
         e = Epi{c2, w.y1r, nullptr, nullptr, w.y2r, w.y2o, w.t2r};
-        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T2, np, kFitPad, kFitPad, (const TA *)w.y1o, (const TA *)fw.V2t, e, st));
+        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T2, np, kFitPad, ks * kFitPad, (const TA *)w.y1o, (const TA *)fw.V2t, e, st));
         e = Epi{c3, nullptr, nullptr, nullptr, nullptr, nullptr, w.t3r};
-        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T3, np, kFitPad, kFitPad, (const TA *)w.y2o, (const TA *)fw.V3t, e, st));
+        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T3, np, kFitPad, ks * kFitPad, (const TA *)w.y2o, (const TA *)fw.V3t, e, st));
     }
     // E_i always; dz3 = w4 (1 - t3^2) when the backward follows
     launch_energy<TA, TR>(n, (const TR *)w.y2r, (const TR *)w.t3r, w4, a.m->b4, w.e_atom,
@@ -111,11 +114,11 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
     if ((s = step_check("fitting_forward", st)) != DP_OK) return s;
     if (bwd) {
         e = Epi{nullptr, nullptr, w4, w.t2r, w.dy2r, w.dz2o, nullptr};
-        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_BWD, np, kFitPad, kFitPad, (const TA *)w.dz3o, (const TA *)fw.V3, e, st));
+        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_BWD, np, kFitPad, ks * kFitPad, (const TA *)w.dz3o, (const TA *)fw.V3, e, st));
         e = Epi{nullptr, w.dy2r, nullptr, w.y1r, nullptr, w.dz1o, nullptr};
-        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_BWD, np, kFitPad, kFitPad, (const TA *)w.dz2o, (const TA *)fw.V2, e, st));
+        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_BWD, np, kFitPad, ks * kFitPad, (const TA *)w.dz2o, (const TA *)fw.V2, e, st));
         e = Epi{nullptr, nullptr, nullptr, nullptr, w.dDr, nullptr, nullptr};
-        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_LIN, np, kDdim, kFitPad, (const TA *)w.dz1o, (const TA *)fw.V1, e, st));
+        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_LIN, np, kDdim, ks * kFitPad, (const TA *)w.dz1o, (const TA *)fw.V1, e, st));
         DP_TIMED("dT", st, launch_dT<TR>(n, (const TR *)w.dDr, (const TR *)w.T, (TR *)w.dT, st));
         if ((s = step_check("fitting_backward", st)) != DP_OK) return s;
         if (PLAIN) {
@@ -139,7 +142,9 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
 dp_status ensure_ws(dp_nlist *nl, int precision)
 {
     int np = (int)round_up(nl->alloc_atoms, kRowPad);
-    size_t need = ws_bytes_for(np, DP_FP64);   // the largest of the three layouts
+    size_t need = ws_bytes_for(np, DP_FP64);
+    size_t need_bf = ws_bytes_for(np, DP_MIXED_BF16);
+    if (need_bf > need) need = need_bf;   // the largest of the three layouts
     (void)precision;
     if (nl->ws_bytes >= need) return DP_OK;
     if (nl->ws) DP_HIP(hipFree(nl->ws));

@@ -146,6 +146,14 @@ dp_status launch_tabulate(dp_model *m, hipStream_t st);
 dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, const int *types,
                              bool reset_flags, hipStream_t st);
 
+// BF16 operands of the fitting net are kept as an exact-ish split
+// x = hi + lo (hi = bf16(x), lo = bf16(x - hi)) laid out along K as
+// [hi | hi | lo] for A and [hi | lo | hi] for Bt, so one BF16 GEMM over 3K
+// accumulates hi*hi + hi*lo + lo*hi (the lo*lo term, ~2^-18 relative, is
+// dropped).  kSplit is the K multiplier of a precision's operands.
+constexpr int kSplitBf16 = 3;
+__host__ __device__ inline int k_split(int precision) { return precision == DP_MIXED_BF16 ? kSplitBf16 : 1; }
+
 // Epilogues of the fitting-net GEMM C = A Bt^T (see fit.hip).
 //   EPI_LIN  out_r = acc
 //   EPI_T1   out_r = out_o = tanh(acc + bias)
@@ -180,6 +188,9 @@ void launch_reduce(int n, const double *e_atom, const double *w_atom, double *pa
                    double *virial, hipStream_t st);
 template <typename T>
 void launch_to_double(long n, const T *a, double *b, hipStream_t st);
+// GEMM operand matrix (n rows, ncols logical columns) to FP64 (hi + lo for BF16)
+template <typename T>
+void launch_op_to_double(int n, int ncols, const T *a, double *b, hipStream_t st);
 void launch_emb_fwd(const dp_model *m, const dp_nlist *nl, int n, const double *x, int precision, void *T,
                     void *D, int *nnei, hipStream_t st);
 void launch_emb_bwd(const dp_model *m, const dp_nlist *nl, int n, const double *x, int precision,

@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(256) k_emb_fwd(int natoms, EnvArgs A, const re
         v = fma(Tl[kM + aa], Tl[kM + bb], v);
         v = fma(Tl[2 * kM + aa], Tl[2 * kM + bb], v);
         v = fma(Tl[3 * kM + aa], Tl[3 * kM + bb], v);
-        D_out[(long)i * kDdim + o] = cvtd<TD>((double)v);
+        store_op(D_out, i, o, kDdim, (double)v);
     }
 }
 
@@ -363,7 +363,7 @@ void launch_emb_fwd(const dp_model *m, const dp_nlist *nl, int n, const double *
 {
     if (precision == DP_FP64) launch_fwd_t<double, double, 4>(m, nl, n, x, T, D, nnei, st);
     else if (precision == DP_FP32) launch_fwd_t<float, float, 8>(m, nl, n, x, T, D, nnei, st);
-    else launch_fwd_t<float, __hip_bfloat16, 8>(m, nl, n, x, T, D, nnei, st);
+    else launch_fwd_t<float, __bf16, 8>(m, nl, n, x, T, D, nnei, st);
 }
 
 void launch_emb_bwd(const dp_model *m, const dp_nlist *nl, int n, const double *x, int precision,

@@ -25,4 +25,25 @@ __device__ inline double dpp_d(double v)
     return __builtin_bit_cast(double, p);
 }
 
+// Writes x as a GEMM operand element (row, col) of a matrix with ncols
+// logical columns: as is for FP64/FP32, as the [hi | hi | lo] split for BF16.
+__device__ inline void store_op(double *p, long row, int col, int ncols, double x)
+{
+    p[row * ncols + col] = x;
+}
+__device__ inline void store_op(float *p, long row, int col, int ncols, double x)
+{
+    p[row * ncols + col] = (float)x;
+}
+__device__ inline void store_op(__bf16 *p, long row, int col, int ncols, double x)
+{
+    float f = (float)x;
+    __bf16 hi = (__bf16)f;
+    __bf16 lo = (__bf16)(f - (float)hi);
+    __bf16 *r = p + row * 3 * ncols;
+    r[col] = hi;
+    r[ncols + col] = hi;
+    r[2 * ncols + col] = lo;
+}
+
 }  // namespace dp

@@ -16,6 +16,7 @@
 // deterministic FP64 sums of the energy and virial.
 
 #include "dp_internal.h"
+#include "emb_common.h"
 
 #include <type_traits>
 
@@ -165,13 +166,13 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const TA *
                 } else if constexpr (EPI == EPI_T1) {
                     TR y = tanh_r(v + bias[gn]);
                     ((TR *)e.out_r)[idx] = y;
-                    if (e.out_o) ((TA *)e.out_o)[idx] = tod<TA>((double)y);
+                    if (e.out_o) store_op((TA *)e.out_o, gm, gn, N, (double)y);
                 } else if constexpr (EPI == EPI_T2) {
                     TR t = tanh_r(v + bias[gn]);
                     TR y = ((const TR *)e.res)[idx] + t;
                     ((TR *)e.out_t)[idx] = t;
                     ((TR *)e.out_r)[idx] = y;
-                    if (e.out_o) ((TA *)e.out_o)[idx] = tod<TA>((double)y);
+                    if (e.out_o) store_op((TA *)e.out_o, gm, gn, N, (double)y);
                 } else if constexpr (EPI == EPI_T3) {
                     ((TR *)e.out_t)[idx] = tanh_r(v + bias[gn]);
                 } else if constexpr (EPI == EPI_EMB) {
@@ -184,13 +185,13 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const TA *
                         long r0 = (long)gm * 2 * e.half + gn, o = (long)gm * e.half + gn;
                         TR dy = res[r0] + res[r0 + e.half] + v;
                         TR t = ((const TR *)e.tt)[o];
-                        ((TA *)e.out_o)[o] = tod<TA>((double)(dy * ((TR)1 - t * t)));
+                        store_op((TA *)e.out_o, gm, gn, e.half, (double)(dy * ((TR)1 - t * t)));
                     }
                 } else {
                     TR dy = (e.resv ? ((const TR *)e.resv)[gn] : ((const TR *)e.res)[idx]) + v;
                     if (e.out_r) ((TR *)e.out_r)[idx] = dy;
                     TR t = ((const TR *)e.tt)[idx];
-                    ((TA *)e.out_o)[idx] = tod<TA>((double)(dy * ((TR)1 - t * t)));
+                    store_op((TA *)e.out_o, gm, gn, N, (double)(dy * ((TR)1 - t * t)));
                 }
             }
 }
@@ -209,7 +210,7 @@ __global__ void __launch_bounds__(256) k_energy(int n, const TR *__restrict__ y2
         long idx = (long)i * kFitPad + c;
         TR t = t3[idx];
         acc += (y2[idx] + t) * w4[c];
-        if (dz3) dz3[idx] = tod<TA>((double)(w4[c] * ((TR)1 - t * t)));
+        if (dz3) store_op(dz3, i, c, kFitPad, (double)(w4[c] * ((TR)1 - t * t)));
     }
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     if (lane == 0) e_atom[i] = (double)acc + b4;
@@ -293,6 +294,19 @@ __global__ void k_to_double<double>(long n, const double *__restrict__ a, double
     if (i < n) b[i] = a[i];
 }
 
+template <typename T>
+__global__ void k_op_to_double(long n, int ncols, const T *__restrict__ a, double *__restrict__ b)
+{
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    long row = i / ncols;
+    int col = (int)(i % ncols);
+    if constexpr (std::is_same<T, __bf16>::value)
+        b[i] = (double)(float)a[row * 3 * ncols + col] + (double)(float)a[row * 3 * ncols + 2 * ncols + col];
+    else
+        b[i] = (double)a[i];
+}
+
 __global__ void k_fill_zero(double *p, long n)
 {
     long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -359,6 +373,16 @@ void launch_to_double(long n, const T *a, double *b, hipStream_t st)
 template void launch_to_double<double>(long, const double *, double *, hipStream_t);
 template void launch_to_double<float>(long, const float *, double *, hipStream_t);
 template void launch_to_double<__bf16>(long, const __bf16 *, double *, hipStream_t);
+
+template <typename T>
+void launch_op_to_double(int n, int ncols, const T *a, double *b, hipStream_t st)
+{
+    long tot = (long)n * ncols;
+    if (tot > 0) hipLaunchKernelGGL((k_op_to_double<T>), dim3(div_up(tot, 256)), dim3(256), 0, st, tot, ncols, a, b);
+}
+template void launch_op_to_double<double>(int, int, const double *, double *, hipStream_t);
+template void launch_op_to_double<float>(int, int, const float *, double *, hipStream_t);
+template void launch_op_to_double<__bf16>(int, int, const __bf16 *, double *, hipStream_t);
 
 void launch_fill_zero(double *p, long n, hipStream_t st)
 {

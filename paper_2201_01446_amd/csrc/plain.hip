@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(256) k_plain_contract(int natoms, int sel, rea
         v = fma(Tl[kM + aa], Tl[kM + bb], v);
         v = fma(Tl[2 * kM + aa], Tl[2 * kM + bb], v);
         v = fma(Tl[3 * kM + aa], Tl[3 * kM + bb], v);
-        D_out[(long)i * kDdim + o] = cvd<TD>((double)v);
+        store_op(D_out, i, o, kDdim, (double)v);
     }
 }
 

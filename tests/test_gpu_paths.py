@@ -146,16 +146,25 @@ def test_autograd_500k_fp32_sampled(P, model, cu_cfg, cu_params):
 # -------------------------------------------------------------------- NVE
 
 def test_nve_fp32_energy_conservation(P, cu_cfg):
-    """FP32 forces, FP64 integration and reductions: total energy stays
-    within 1e-4 of the kinetic energy over 50 steps (forces of copper's size)."""
+    """FP32 forces, FP64 integration and reductions.  The same 50-step
+    trajectory in FP64 gives the integrator's own energy error; the FP32 run
+    may exceed it only by the FP32 rounding of the potential energy (the
+    output weights are scaled up so forces are of copper's size, which also
+    puts a large constant into E)."""
     p = synth.model_params(cu_cfg)
     synth.split_params(cu_cfg, p)["w4"][:] *= 2000.0
     m = P.Model(cu_cfg, p).tabulate(S_MAX, H, TAIL, H_TAIL)
     x0, box = synth.copper(4, 0.05, 3)
     v0 = synth.maxwell_boltzmann(len(x0), 330.0, seed=4)
-    x, v = dev(x0), dev(v0)
-    nl = P.NeighborList(m, x, box)
-    th = P.nve_run(m, nl, x, v, box, synth.M_CU, 1.0, 50, rebuild_every=10, precision=P.FP32).cpu().numpy()
-    et = th.sum(1)
-    print(f"nve fp32: max |E - E0| {np.max(np.abs(et - et[0])):.3g} eV, KE0 {th[0, 1]:.3g} eV")
-    assert np.max(np.abs(et - et[0])) < 1e-3 * th[0, 1]
+    dev_e = {}
+    for prec in (P.FP64, P.FP32):
+        x, v = dev(x0), dev(v0)
+        nl = P.NeighborList(m, x, box)
+        th = P.nve_run(m, nl, x, v, box, synth.M_CU, 1.0, 50, rebuild_every=10, precision=prec).cpu().numpy()
+        et = th.sum(1)
+        dev_e[prec] = (np.max(np.abs(et - et[0])), abs(th[0, 0]), th[0, 1])
+    d64, pe, ke = dev_e[P.FP64]
+    d32 = dev_e[P.FP32][0]
+    print(f"nve: max |E - E0| fp64 {d64:.3g} eV, fp32 {d32:.3g} eV, |PE| {pe:.3g} eV, KE0 {ke:.3g} eV")
+    assert d64 < 1e-3 * ke
+    assert d32 <= d64 + 2e-7 * pe
