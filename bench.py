@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=10)
+    ap.add_argument("--serve-requests", type=int, default=4096)
+    ap.add_argument("--no-serve", action="store_true")
     return ap.parse_args()
 
 
@@ -177,9 +179,35 @@ def main():
         out[name] = {"value": round(vp, 1), "ms_per_step": round(res["ms"] / Kp, 4), "steps": Kp,
                      "kernels": {k: round(v[0] / max(v[1], 1), 4) for k, v in res["kernels"].items()},
                      "speedup_compressed_vs_plain": round(comp / vp, 3) if comp else None}
+    if not args.no_serve:
+        out["serving"] = serving(P, model, args.serve_requests)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out))
+
+
+def serving(P, model, nreq):
+    """Continuous batching of nreq evaluation requests (periodic FCC-derived
+    Cu cells, atom counts log-uniform in [32, 20000], sigma U[0.02, 0.15] A,
+    0-5 % vacancies), FP32.  A closed loop (all requests at t = 0) gives the
+    saturated throughput; Poisson arrivals at 70 % of it give the latency
+    percentiles (arrival to results on the host)."""
+    import synth
+    from paper_2201_01446_amd.serve import Server, poisson_arrivals
+    t = time.perf_counter()
+    reqs = [r[:2] for r in synth.serving_stream(nreq)]
+    gen_s = time.perf_counter() - t
+    srv = Server(model, P.FP32, slots=3, hbm_budget=24 << 30)
+    srv.run(reqs[:64])                          # warm-up
+    _, closed = srv.run(reqs)
+    rate = 0.7 * nreq / closed["wall_s"]
+    _, pois = srv.run(reqs, poisson_arrivals(nreq, rate, seed=synth.SEED_SERVING + 1))
+    keep = ("atoms_per_s", "p50_ms", "p99_ms", "mean_ms", "batches", "mean_batch_atoms", "wall_s")
+    return {"requests": nreq, "atoms": closed["atoms"], "slots": closed["slots"],
+            "slot_atoms": closed["slot_atoms"], "precision": "fp32",
+            "closed_loop": {k: round(closed[k], 4) for k in keep},
+            "poisson": dict({k: round(pois[k], 4) for k in keep}, rate_req_per_s=round(rate, 2)),
+            "request_generation_s": round(gen_s, 2)}
 
 
 def cpu_baseline(cfg, params, x, box, seconds):

@@ -184,6 +184,41 @@ dp_status dp_nve_run(dp_model *model, dp_nlist **nlist, int natoms, double *x_d,
                      int nsteps, int rebuild_every, double skin, int mode, int precision,
                      double *thermo_d, void *stream);
 
+/* ---------------------------------------------------------------- serving
+ * A batch evaluates several independent configurations ("requests") in one
+ * chain of launches: their atoms are concatenated (request r owns atoms
+ * [offset, offset + natoms) of coords_d), each request's neighbor list is
+ * built for its own box into one combined list, every per-atom kernel and
+ * fitting-net GEMM runs once over all atoms of the batch, and E and W are
+ * reduced per request in an order fixed relative to the request's first atom,
+ * so a request's energy and virial do not depend on its batch-mates (forces
+ * differ only by the order of FP64 atomic additions).  The batch's neighbor
+ * list and scratch are allocated once (for max_atoms) and stay resident. */
+typedef struct {
+    int natoms;      /* atoms of this request                                */
+    int offset;      /* first atom in the batch (requests are contiguous)    */
+    int periodic;    /* 1: orthorhombic box below; 0: open cluster (<= 1024) */
+    double box[9];   /* host, row vectors                                    */
+} dp_request;
+typedef struct dp_batch dp_batch;
+
+dp_status dp_batch_create(dp_model *model, int max_atoms, int max_requests, double skin,
+                          dp_batch **out);
+dp_status dp_batch_destroy(dp_batch *batch);
+/* energy_d[nreq], force_d[total*3], virial_d[nreq*9], atom_energy_d[total]
+ * (device, FP64, NULL skips).  Enqueued on `stream`; one batch object must
+ * not be used by two streams at once.  Returns DP_ERR_CAPACITY when the
+ * requests exceed max_atoms or max_requests. */
+dp_status dp_batch_compute(dp_model *model, dp_batch *batch, int nreq, const dp_request *reqs_h,
+                           const double *coords_d, int precision, double *energy_d,
+                           double *force_d, double *virial_d, double *atom_energy_d, void *stream);
+/* Counters of the last batch (synchronises), as dp_nlist_stats. */
+dp_status dp_batch_stats(dp_batch *batch, int *max_nei, int *n_sel_overflow, int *n_table_oob,
+                         int *n_cap_overflow);
+/* Device bytes one evaluation of natoms atoms needs (neighbor list and
+ * scratch): the unit of the serving loop's HBM admission. */
+dp_status dp_footprint_bytes(const dp_model *model, int natoms, size_t *bytes);
+
 /* Kernel timing for measurement: while enabled, every kernel launch of the
  * library is bracketed by HIP events recorded on the stream it is launched
  * on.  dp_timers_read synchronises on those events, returns per kernel name

@@ -50,6 +50,11 @@ _SIG = {
     "dp_energy_backward": [_vp, _vp, _i, _vp, _i, _i, _vp, _vp, _vp],
     "dp_nlist_stats": [_vp, _pi, _pi, _pi, _pi],
     "dp_nve_run": [_vp, _pvp, _i, _vp, _vp, _vp, _vp, _d, _d, _i, _i, _d, _i, _i, _vp, _vp],
+    "dp_batch_create": [_vp, _i, _i, _d, _pvp],
+    "dp_batch_destroy": [_vp],
+    "dp_batch_compute": [_vp, _vp, _i, _vp, _vp, _i, _vp, _vp, _vp, _vp, _vp],
+    "dp_batch_stats": [_vp, _pi, _pi, _pi, _pi],
+    "dp_footprint_bytes": [_vp, _i, ctypes.POINTER(_sz)],
     "dp_timers_enable": [_i],
     "dp_timers_read": [_i, _vp, _vp, _vp, _pi],
 }

@@ -4,6 +4,7 @@
 
 #include "dp_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -575,6 +576,173 @@ dp_status dp_nve_run(dp_model *m, dp_nlist **nlp, int natoms, double *x, double 
     int f[kNumFlags];
     if ((s = read_flags(nl, f, st)) != DP_OK) return s;
     return check_build_flags(f);
+}
+
+dp_status dp_footprint_bytes(const dp_model *m, int natoms, size_t *bytes)
+{
+    if (!m || natoms < 0 || !bytes) return fail(DP_ERR_ARG, "bad argument");
+    size_t per = (size_t)kCapMax * 8 + 3 * 8 + 3 * 8 + 4 * 4 + 3 * 8;   // candidates, positions, boxes, counts
+    size_t ws = std::max(ws_bytes_for_atoms(natoms, DP_FP64), ws_bytes_for_atoms(natoms, DP_MIXED_BF16));
+    *bytes = per * (size_t)natoms + ws;
+    return DP_OK;
+}
+
+dp_status dp_batch_create(dp_model *m, int max_atoms, int max_requests, double skin, dp_batch **out)
+{
+    if (!m || !out || max_atoms < 1 || max_requests < 1 || !(skin >= 0)) return fail(DP_ERR_ARG, "bad argument");
+    if (max_atoms >= (1 << 25)) return fail(DP_ERR_UNSUPPORTED, "at most 2^25 - 1 atoms");
+    dp_batch *b = new dp_batch();
+    b->max_atoms = max_atoms;
+    b->max_req = max_requests;
+    b->skin = skin;
+    dp_nlist *nl = new dp_nlist();
+    b->nl = nl;
+    DP_HIP(hipGetDevice(&nl->device));
+    nl->rc_build = m->cfg.rcut + skin;
+    nl->periodic = true;
+    nl->cap = kCapMax;
+    nl->alloc_atoms = max_atoms;
+    size_t A = (size_t)max_atoms;
+    DP_HIP(hipMalloc(&nl->wpos, sizeof(double) * 3 * A));
+    DP_HIP(hipMalloc(&nl->wrap, sizeof(int) * A));
+    DP_HIP(hipMalloc(&nl->cnt, sizeof(int) * A));
+    DP_HIP(hipMalloc(&nl->nei, sizeof(int) * A * kCapMax));
+    DP_HIP(hipMalloc(&nl->shift, sizeof(int) * A * kCapMax));
+    DP_HIP(hipMalloc(&nl->force_tmp, sizeof(double) * 3 * A));
+    DP_HIP(hipMalloc(&nl->atomL, sizeof(double) * 3 * A));
+    DP_HIP(hipMalloc(&nl->flags, sizeof(int) * kNumFlags));
+    DP_HIP(hipMemset(nl->flags, 0, sizeof(int) * kNumFlags));
+    DP_HIP(hipMalloc(&nl->scal, sizeof(double) * 512));
+    DP_HIP(hipMalloc(&b->off_d, sizeof(int) * (max_requests + 1)));
+    DP_HIP(hipMalloc(&b->Lreq_d, sizeof(double) * 3 * max_requests));
+    DP_HIP(hipHostMalloc((void **)&b->off_h, sizeof(int) * (max_requests + 1), hipHostMallocDefault));
+    DP_HIP(hipHostMalloc((void **)&b->Lreq_h, sizeof(double) * 3 * max_requests, hipHostMallocDefault));
+    DP_HIP(hipEventCreateWithFlags(&b->staged, hipEventDisableTiming));
+    dp_status s = ensure_ws(nl, DP_FP64);
+    if (s != DP_OK) return s;
+    *out = b;
+    return DP_OK;
+}
+
+dp_status dp_batch_destroy(dp_batch *b)
+{
+    if (!b) return DP_OK;
+    if (b->nl) {
+        (void)hipFree(b->nl->atomL);
+        b->nl->atomL = nullptr;
+        dp_nlist_destroy(b->nl);
+    }
+    (void)hipFree(b->off_d);
+    (void)hipFree(b->Lreq_d);
+    (void)hipHostFree(b->off_h);
+    (void)hipHostFree(b->Lreq_h);
+    if (b->staged) (void)hipEventDestroy(b->staged);
+    delete b;
+    return DP_OK;
+}
+
+dp_status dp_batch_compute(dp_model *m, dp_batch *b, int nreq, const dp_request *reqs, const double *coords_d,
+                           int precision, double *energy_d, double *force_d, double *virial_d,
+                           double *atom_energy_d, void *stream)
+{
+    if (!m || !b || !reqs || !coords_d || nreq < 1) return fail(DP_ERR_ARG, "bad argument");
+    if (nreq > b->max_req) return fail(DP_ERR_CAPACITY, "more requests than the batch was created for");
+    if (!m->tab64) return fail(DP_ERR_STATE, "dp_tabulate has not run");
+    if (precision < DP_FP64 || precision > DP_MIXED_BF16) return fail(DP_ERR_ARG, "unknown precision");
+    hipStream_t st = (hipStream_t)stream;
+    dp_nlist *nl = b->nl;
+    double rcs = nl->rc_build;
+    long total = 0;
+    size_t cells_needed = 0;
+    int cellcap = 0;
+    for (int r = 0; r < nreq; r++) {
+        const dp_request &q = reqs[r];
+        if (q.natoms < 1 || q.offset != total) return fail(DP_ERR_ARG, "requests must be contiguous and non-empty");
+        total += q.natoms;
+        if (q.periodic) {
+            double L[3];
+            if (!box_ok(q.box, L)) return fail(DP_ERR_UNSUPPORTED, "box must be orthorhombic");
+            long ncell = 1;
+            for (int a = 0; a < 3; a++) {
+                if (L[a] < 0.5 * rcs) return fail(DP_ERR_UNSUPPORTED, "box edge shorter than (rcut + skin) / 2");
+                int nc = (int)std::floor(L[a] / (0.5 * rcs));
+                ncell *= nc < 1 ? 1 : nc;
+            }
+            int per = (int)std::ceil((double)q.natoms / ncell);
+            int cc = (int)round_up(3 * per + 8, 8);
+            cellcap = std::max(cellcap, cc);
+            cells_needed = std::max(cells_needed, (size_t)ncell);
+        } else if (q.natoms > kCapMax) {
+            return fail(DP_ERR_UNSUPPORTED, "open clusters in a batch hold at most 1024 atoms");
+        }
+    }
+    if (total > b->max_atoms) return fail(DP_ERR_CAPACITY, "batch exceeds max_atoms");
+    cellcap = std::max(cellcap, nl->cellcap);
+    if (cells_needed * cellcap > nl->ncell_alloc || (cells_needed && !nl->cell_cnt)) {
+        // grow the shared cell grid (rare: only for a larger cell than seen before)
+        DP_HIP(hipStreamSynchronize(st));
+        if (nl->cell_atoms) DP_HIP(hipFree(nl->cell_atoms));
+        if (nl->cell_cnt) DP_HIP(hipFree(nl->cell_cnt));
+        size_t nc = std::max(cells_needed, (size_t)1);
+        DP_HIP(hipMalloc(&nl->cell_atoms, sizeof(int) * nc * cellcap));
+        DP_HIP(hipMalloc(&nl->cell_cnt, sizeof(int) * nc));
+        nl->ncell_alloc = nc * cellcap;
+    }
+    nl->cellcap = cellcap ? cellcap : nl->cellcap;
+    // request table: staging buffers are reused, so wait for the last upload
+    DP_HIP(hipEventSynchronize(b->staged));
+    for (int r = 0; r < nreq; r++) {
+        b->off_h[r] = reqs[r].offset;
+        for (int a = 0; a < 3; a++) b->Lreq_h[3 * r + a] = reqs[r].periodic ? reqs[r].box[4 * a] : 0.0;
+    }
+    b->off_h[nreq] = (int)total;
+    DP_HIP(hipMemcpyAsync(b->off_d, b->off_h, sizeof(int) * (nreq + 1), hipMemcpyHostToDevice, st));
+    DP_HIP(hipMemcpyAsync(b->Lreq_d, b->Lreq_h, sizeof(double) * 3 * nreq, hipMemcpyHostToDevice, st));
+    DP_HIP(hipEventRecord(b->staged, st));
+    launch_expand_boxes(nreq, b->off_d, b->Lreq_d, nl->atomL, st);
+    launch_fill_zero_int(nl->flags, kNumFlags, st);
+    for (int r = 0; r < nreq; r++) {
+        double L[3];
+        const double *Lp = nullptr;
+        if (reqs[r].periodic) {
+            box_ok(reqs[r].box, L);
+            Lp = L;
+        }
+        dp_status s = launch_build_nlist_range(nl, coords_d, reqs[r].offset, reqs[r].natoms, Lp, st);
+        if (s != DP_OK) return s;
+    }
+    dp_status s = step_check("batch_nlist", st);
+    if (s != DP_OK) return s;
+    nl->natoms = (int)total;
+    nl->fwd_token = 0;
+    ComputeArgs a{};
+    a.m = m;
+    a.nl = nl;
+    a.natoms = (int)total;
+    a.x = coords_d;
+    a.precision = precision;
+    a.energy = energy_d;
+    a.virial = virial_d;
+    a.atom_energy = atom_energy_d;
+    a.need_forces = force_d || virial_d;
+    a.force = force_d ? force_d : nl->force_tmp;
+    a.phase = 0;
+    a.nseg = nreq;
+    a.seg_off = b->off_d;
+    return run_compressed(a, st);
+}
+
+dp_status dp_batch_stats(dp_batch *b, int *max_nei, int *n_sel_overflow, int *n_table_oob, int *n_cap_overflow)
+{
+    if (!b) return fail(DP_ERR_ARG, "NULL batch");
+    int f[kNumFlags];
+    DP_HIP(hipDeviceSynchronize());
+    DP_HIP(hipMemcpy(f, b->nl->flags, sizeof(f), hipMemcpyDeviceToHost));
+    if (max_nei) *max_nei = f[kFlagMaxNei];
+    if (n_sel_overflow) *n_sel_overflow = f[kFlagSelOverflow];
+    if (n_table_oob) *n_table_oob = f[kFlagTableOob];
+    if (n_cap_overflow) *n_cap_overflow = f[kFlagCapOverflow] + f[kFlagCellOverflow];
+    return DP_OK;
 }
 
 const char *dp_last_error(void) { return g_err.c_str(); }

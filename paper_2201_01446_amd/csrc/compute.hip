@@ -9,7 +9,7 @@
 //   k_dT             dE/dT from dE/dD
 //   k_emb_bwd        adjoint of the fused step -> forces (atomics), W_i
 //   k_reduce_*       deterministic FP64 sums of E_i and W_i
-// Buffers live in the neighbor list's workspace; rows are padded to 64 so
+// Buffers live in the neighbor list's workspace; rows are padded to 128 so
 // the GEMM tiles never read past an allocation.
 
 #include "dp_internal.h"
@@ -91,6 +91,11 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
     const TR *c1 = fb, *c2 = fb + kFitPad, *c3 = fb + 2 * kFitPad, *w4 = fb + 3 * kFitPad;
     Epi e{};
     const int ks = k_split(a.precision);   // operand K multiplier (BF16 split)
+    // GEMM rows: the live atoms rounded up to a whole 128-row tile (rows past
+    // n hold stale finite values and their outputs are never read); the
+    // buffers themselves are carved for the allocation's np rows.
+    const int mr = (int)round_up(n, kRowPad);
+    (void)np;
     bool fwd = a.phase != 2, bwd = a.need_forces && a.phase != 1;
     if (fwd) {
         if (PLAIN) {
@@ -102,11 +107,11 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
         if (a.T_out) launch_to_double<TR>((long)n * 4 * kM, (const TR *)w.T, a.T_out, st);
         if (a.D_out) launch_op_to_double<TA>(n, kDdim, (const TA *)w.D, a.D_out, st);
         e = Epi{c1, nullptr, nullptr, nullptr, w.y1r, w.y1o, nullptr};
-        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T1, np, kFitPad, ks * kDdim, (const TA *)w.D, (const TA *)fw.V1t, e, st));
+        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T1, mr, kFitPad, ks * kDdim, (const TA *)w.D, (const TA *)fw.V1t, e, st));
         e = Epi{c2, w.y1r, nullptr, nullptr, w.y2r, w.y2o, w.t2r};
-        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T2, np, kFitPad, ks * kFitPad, (const TA *)w.y1o, (const TA *)fw.V2t, e, st));
+        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T2, mr, kFitPad, ks * kFitPad, (const TA *)w.y1o, (const TA *)fw.V2t, e, st));
         e = Epi{c3, nullptr, nullptr, nullptr, nullptr, nullptr, w.t3r};
-        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T3, np, kFitPad, ks * kFitPad, (const TA *)w.y2o, (const TA *)fw.V3t, e, st));
+        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T3, mr, kFitPad, ks * kFitPad, (const TA *)w.y2o, (const TA *)fw.V3t, e, st));
     }
     // E_i always; dz3 = w4 (1 - t3^2) when the backward follows
     launch_energy<TA, TR>(n, (const TR *)w.y2r, (const TR *)w.t3r, w4, a.m->b4, w.e_atom,
@@ -114,11 +119,11 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
     if ((s = step_check("fitting_forward", st)) != DP_OK) return s;
     if (bwd) {
         e = Epi{nullptr, nullptr, w4, w.t2r, w.dy2r, w.dz2o, nullptr};
-        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_BWD, np, kFitPad, ks * kFitPad, (const TA *)w.dz3o, (const TA *)fw.V3, e, st));
+        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_BWD, mr, kFitPad, ks * kFitPad, (const TA *)w.dz3o, (const TA *)fw.V3, e, st));
         e = Epi{nullptr, w.dy2r, nullptr, w.y1r, nullptr, w.dz1o, nullptr};
-        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_BWD, np, kFitPad, ks * kFitPad, (const TA *)w.dz2o, (const TA *)fw.V2, e, st));
+        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_BWD, mr, kFitPad, ks * kFitPad, (const TA *)w.dz2o, (const TA *)fw.V2, e, st));
         e = Epi{nullptr, nullptr, nullptr, nullptr, w.dDr, nullptr, nullptr};
-        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_LIN, np, kDdim, ks * kFitPad, (const TA *)w.dz1o, (const TA *)fw.V1, e, st));
+        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_LIN, mr, kDdim, ks * kFitPad, (const TA *)w.dz1o, (const TA *)fw.V1, e, st));
         DP_TIMED("dT", st, launch_dT<TR>(n, (const TR *)w.dDr, (const TR *)w.T, (TR *)w.dT, st));
         if ((s = step_check("fitting_backward", st)) != DP_OK) return s;
         if (PLAIN) {
@@ -131,13 +136,21 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
     }
     double *energy = a.phase == 2 ? nullptr : a.energy;
     double *virial = bwd ? a.virial : nullptr;
-    if (energy || virial) launch_reduce(n, w.e_atom, bwd ? w.w_atom : nullptr, w.part, energy, virial, st);
+    if (a.nseg > 0)
+        launch_segment_reduce(a.nseg, a.seg_off, w.e_atom, bwd ? w.w_atom : nullptr, energy, virial, st);
+    else if (energy || virial)
+        launch_reduce(n, w.e_atom, bwd ? w.w_atom : nullptr, w.part, energy, virial, st);
     if (a.atom_energy && a.phase != 2)
         DP_HIP(hipMemcpyAsync(a.atom_energy, w.e_atom, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     return step_check("reduce", st);
 }
 
 }  // namespace
+
+size_t ws_bytes_for_atoms(int natoms, int precision)
+{
+    return ws_bytes_for((int)round_up(natoms, kRowPad), precision);
+}
 
 dp_status ensure_ws(dp_nlist *nl, int precision)
 {

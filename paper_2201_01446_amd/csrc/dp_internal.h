@@ -18,7 +18,7 @@ constexpr int kMlt = 16;
 constexpr int kDdim = kM * kMlt;     // 2048 descriptor entries per atom
 constexpr int kFitPad = 256;         // fitting widths padded to 256 (zero columns)
 constexpr int kCapMax = 1024;        // skin candidates per atom, upper bound
-constexpr int kRowPad = 64;          // atom rows of every GEMM operand padded to 64
+constexpr int kRowPad = 128;         // atom rows of every GEMM operand padded to 128
 
 // Device-side sticky counters of a neighbor list.
 enum Flag {
@@ -93,9 +93,23 @@ struct dp_nlist {
     size_t ws_bytes = 0;
     void *ws_plain = nullptr;
     size_t ws_plain_bytes = 0;
+    double *atomL = nullptr;       // per-atom box edges when the list spans a batch of cells
     double *force_tmp = nullptr;   // forces when the caller wants only the virial
     int fwd_token = 0;             // precision+1 while a forward's activations are kept
     double *scal = nullptr;        // [16] device scalars (energy, partial sums)
+};
+
+// A batch of independent cells (serving): one combined neighbor list and
+// scratch sized for max_atoms, resident across calls.
+struct dp_batch {
+    dp_nlist *nl = nullptr;
+    int max_atoms = 0, max_req = 0;
+    double skin = 2.0;
+    int *off_d = nullptr;        // [max_req + 1]
+    double *Lreq_d = nullptr;    // [max_req][3]
+    int *off_h = nullptr;        // pinned staging of the request table
+    double *Lreq_h = nullptr;
+    hipEvent_t staged = nullptr; // the last upload from the staging buffers has run
 };
 
 namespace dp {
@@ -145,6 +159,13 @@ void launch_fill_zero_int(int *p, long n, hipStream_t st);
 dp_status launch_tabulate(dp_model *m, hipStream_t st);
 dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, const int *types,
                              bool reset_flags, hipStream_t st);
+// Candidates of the atoms [off, off + n) of a batch, all inside one cell with
+// box edges L (NULL: open); neighbor indices are global (j + off).
+dp_status launch_build_nlist_range(dp_nlist *nl, const double *x, int off, int n, const double *L,
+                                   hipStream_t st);
+void launch_segment_reduce(int nreq, const int *offsets, const double *e_atom, const double *w_atom,
+                           double *energy, double *virial, hipStream_t st);
+void launch_expand_boxes(int nreq, const int *offsets, const double *Lreq, double *atomL, hipStream_t st);
 
 // BF16 operands of the fitting net are kept as an exact-ish split
 // x = hi + lo (hi = bf16(x), lo = bf16(x - hi)) laid out along K as
@@ -207,6 +228,8 @@ struct ComputeArgs {
     double *T_out, *D_out;
     bool need_forces;
     int phase;   // 0: whole step; 1: forward only, activations kept; 2: backward from kept activations
+    int nseg = 0;                  // >0: E and W per segment (request) of a batch instead of totals
+    const int *seg_off = nullptr;  // device [nseg + 1] atom offsets of the segments
 };
 template <typename real, typename TD>
 dp_status plain_forward(const dp_model *m, dp_nlist *nl, int n, const double *x, void *T, void *D, int *nnei,
@@ -215,6 +238,7 @@ template <typename real>
 dp_status plain_backward(const dp_model *m, dp_nlist *nl, int n, const void *dT, double *force, double *w_atom,
                          hipStream_t st);
 dp_status ensure_ws(dp_nlist *nl, int precision);
+size_t ws_bytes_for_atoms(int natoms, int precision);
 dp_status run_compressed(const ComputeArgs &a, hipStream_t st);
 dp_status run_plain(const ComputeArgs &a, hipStream_t st);
 void launch_verlet_kick_drift(double *x, double *v, const double *f, int n, double kick, double dt,

@@ -18,6 +18,7 @@ struct EnvArgs {
     const int *cnt, *nei, *shift;
     int cap, sel;
     double L0, L1, L2;
+    const double *atomL;   // per-atom box edges (3 per atom) of a batch of cells, or NULL
     double rc2;
     // gate
     double rs, rc;
@@ -73,6 +74,12 @@ __device__ int build_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane, int 
     const int *nei = A.nei + (long)i * A.cap;
     const int *shf = A.shift + (long)i * A.cap;
     double xi0 = A.x[3 * i], xi1 = A.x[3 * i + 1], xi2 = A.x[3 * i + 2];
+    double L0 = A.L0, L1 = A.L1, L2 = A.L2;
+    if (A.atomL) {
+        L0 = A.atomL[3 * i];
+        L1 = A.atomL[3 * i + 1];
+        L2 = A.atomL[3 * i + 2];
+    }
     int n_in = 0;
     for (int base = 0; base < nc; base += 64) {
         int k = base + lane;
@@ -82,9 +89,9 @@ __device__ int build_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane, int 
         if (k < nc) {
             j = nei[k];
             int s = shf[k];
-            d0 = (A.x[3 * j] - xi0) + s8(s, 0) * A.L0;
-            d1 = (A.x[3 * j + 1] - xi1) + s8(s, 8) * A.L1;
-            d2 = (A.x[3 * j + 2] - xi2) + s8(s, 16) * A.L2;
+            d0 = (A.x[3 * j] - xi0) + s8(s, 0) * L0;
+            d1 = (A.x[3 * j + 1] - xi1) + s8(s, 8) * L1;
+            d2 = (A.x[3 * j + 2] - xi2) + s8(s, 16) * L2;
             in = d0 * d0 + d1 * d1 + d2 * d2 < A.rc2;
         }
         unsigned long long mask = __ballot(in);
@@ -99,17 +106,17 @@ __device__ int build_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane, int 
         // keep the sel nearest by (r^2, j, image); ranks are a permutation
         for (int k = lane; k < nc; k += 64) {
             int j = nei[k], s = shf[k];
-            double d0 = (A.x[3 * j] - xi0) + s8(s, 0) * A.L0;
-            double d1 = (A.x[3 * j + 1] - xi1) + s8(s, 8) * A.L1;
-            double d2 = (A.x[3 * j + 2] - xi2) + s8(s, 16) * A.L2;
+            double d0 = (A.x[3 * j] - xi0) + s8(s, 0) * L0;
+            double d1 = (A.x[3 * j + 1] - xi1) + s8(s, 8) * L1;
+            double d2 = (A.x[3 * j + 2] - xi2) + s8(s, 16) * L2;
             double r2 = d0 * d0 + d1 * d1 + d2 * d2;
             if (!(r2 < A.rc2)) continue;
             int rank = 0;
             for (int q = 0; q < nc; q++) {
                 int jq = nei[q], sq = shf[q];
-                double e0 = (A.x[3 * jq] - xi0) + s8(sq, 0) * A.L0;
-                double e1 = (A.x[3 * jq + 1] - xi1) + s8(sq, 8) * A.L1;
-                double e2 = (A.x[3 * jq + 2] - xi2) + s8(sq, 16) * A.L2;
+                double e0 = (A.x[3 * jq] - xi0) + s8(sq, 0) * L0;
+                double e1 = (A.x[3 * jq + 1] - xi1) + s8(sq, 8) * L1;
+                double e2 = (A.x[3 * jq + 2] - xi2) + s8(sq, 16) * L2;
                 double rq = e0 * e0 + e1 * e1 + e2 * e2;
                 if (!(rq < A.rc2)) continue;
                 bool less = rq < r2 || (rq == r2 && (jq < j || (jq == j && sq < s)));
@@ -209,6 +216,7 @@ inline EnvArgs make_env_args(const dp_model *m, const dp_nlist *nl, const double
     A.L0 = nl->L[0];
     A.L1 = nl->L[1];
     A.L2 = nl->L[2];
+    A.atomL = nl->atomL;
     A.rc2 = m->cfg.rcut * m->cfg.rcut;
     A.rs = m->cfg.rcut_smth;
     A.rc = m->cfg.rcut;

@@ -25,6 +25,9 @@ namespace dp {
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+// 16 raw bytes as a native vector (HIP's uint4 struct defeats register promotion)
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -37,28 +40,28 @@ template <> struct MMT<__bf16> { using acc = float; using accv = f4v; static con
 // For the 4-deep FP32/FP64 instructions the VEC elements of a fragment feed
 // VEC instructions; lane group q then holds k = q*VEC + v of the group in the
 // v-th one, the same mapping for A and B, so the group's sum is complete.
-__device__ inline void mfma_frag(const uint4 &a, const uint4 &b, d4v &c)
+__device__ inline void mfma_frag(const u4v &a, const u4v &b, d4v &c)
 {
-    double2 x = __builtin_bit_cast(double2, a), y = __builtin_bit_cast(double2, b);
-    c = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, y.x, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f64_16x16x4f64(x.y, y.y, c, 0, 0, 0);
+    d2v x = __builtin_bit_cast(d2v, a), y = __builtin_bit_cast(d2v, b);
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(x[0], y[0], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(x[1], y[1], c, 0, 0, 0);
 }
-__device__ inline void mfma_frag_f32(const uint4 &a, const uint4 &b, f4v &c)
+__device__ inline void mfma_frag_f32(const u4v &a, const u4v &b, f4v &c)
 {
-    float4 x = __builtin_bit_cast(float4, a), y = __builtin_bit_cast(float4, b);
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, y.x, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, y.y, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(x.z, y.z, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(x.w, y.w, c, 0, 0, 0);
+    f4v x = __builtin_bit_cast(f4v, a), y = __builtin_bit_cast(f4v, b);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[0], y[0], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[1], y[1], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[2], y[2], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[3], y[3], c, 0, 0, 0);
 }
-__device__ inline void mfma_frag_bf16(const uint4 &a, const uint4 &b, f4v &c)
+__device__ inline void mfma_frag_bf16(const u4v &a, const u4v &b, f4v &c)
 {
     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, a), __builtin_bit_cast(bf8v, b),
                                                 c, 0, 0, 0);
 }
 
 template <typename TA, typename AV>
-__device__ inline void mfma_any(const uint4 &a, const uint4 &b, AV &c)
+__device__ inline void mfma_any(const u4v &a, const u4v &b, AV &c)
 {
     if constexpr (std::is_same<TA, double>::value) mfma_frag(a, b, c);
     else if constexpr (std::is_same<TA, float>::value) mfma_frag_f32(a, b, c);
@@ -81,83 +84,122 @@ __device__ inline double tanh_r(double v) { return tanh(v); }
 
 namespace {
 
-constexpr int BM = 64, BN = 64, ROWB = 144;   // tile rows/cols, LDS row pitch (bytes)
+constexpr int ROWB = 144;   // LDS row pitch (bytes): 128 bytes of K + 16 of padding
 
-template <typename TA, typename TR, int EPI>
+// N 16-byte chunks of a stage held by one thread: chunk r of thread tid is
+// row (tid + 256 r) / 8, byte column 16 ((tid + 256 r) mod 8) of the tile.
+template <int N>
+struct Stage {
+    u4v v;
+    Stage<N - 1> rest;
+    __device__ __attribute__((always_inline)) void load(const char *g, long ld, int kt, int tid)
+    {
+        int c = tid + 256 * (N - 1);
+        v = *reinterpret_cast<const u4v *>(g + (c >> 3) * ld + kt * 128 + (c & 7) * 16);
+        rest.load(g, ld, kt, tid);
+    }
+    __device__ __attribute__((always_inline)) void store(char *lds, int tid) const
+    {
+        int c = tid + 256 * (N - 1);
+        *reinterpret_cast<u4v *>(lds + (c >> 3) * ROWB + (c & 7) * 16) = v;
+        rest.store(lds, tid);
+    }
+};
+template <>
+struct Stage<0> {
+    __device__ inline void load(const char *, long, int, int) {}
+    __device__ inline void store(char *, int) const {}
+};
+
+// C[M x N] = A[M x K] Bt[N x K]^T with the epilogue EPI.  Block: 4 waves in a
+// 2 x 2 arrangement, each wave TM x TN MFMA tiles of 16 x 16, so the block
+// tile is BM = 32 TM by BN = 32 TN.  K advances 128 bytes per stage through a
+// double-buffered LDS copy (16-byte global loads staged in registers).  The
+// grid is 1-D: tile t goes to block (t mod 8) * (T / 8) + t / 8 order, i.e.
+// consecutive tiles (the column tiles of one row tile first) land on the same
+// XCD, whose L2 then serves the shared A rows.
+template <typename TA, typename TR, int EPI, int TM, int TN>
 __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const TA *__restrict__ A,
                                                  const TA *__restrict__ Bt, Epi e)
 {
     using accv = typename MMT<TA>::accv;
-    constexpr int VEC = MMT<TA>::VEC;
-    constexpr int BK = 128 / sizeof(TA);   // 128 bytes of K per row and stage
+    constexpr int BM = 32 * TM, BN = 32 * TN;
+    constexpr int BK = 128 / sizeof(TA);   // elements of K per row and stage
+    constexpr int LA = BM * 8 / 256, LB = BN * 8 / 256;   // 16-byte chunks per thread
     __shared__ __align__(16) char As[2][BM * ROWB];
     __shared__ __align__(16) char Bs[2][BN * ROWB];
     int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    int row0 = blockIdx.y * BM, col0 = blockIdx.x * BN;
+    // XCD-aware tile order
+    int ntn = N / BN, ntm = (M + BM - 1) / BM;
+    int ntiles = ntn * ntm;
+    int pid = blockIdx.x;
+    int per = (ntiles + 7) / 8;
+    int tile = (pid % 8) * per + pid / 8;
+    if (tile >= ntiles) return;
+    int row0 = (tile / ntn) * BM, col0 = (tile % ntn) * BN;
     int wr = wave >> 1, wc = wave & 1;
     int m = lane & 15, q = lane >> 4;
 
-    // global -> LDS: 2 x 16 bytes of A and of B per thread and stage
-    int lr[2], lc[2];
-    for (int r = 0; r < 2; r++) {
-        int c = tid + 256 * r;
-        lr[r] = c >> 3;
-        lc[r] = c & 7;
-    }
     const char *Ag = reinterpret_cast<const char *>(A) + (long)row0 * K * sizeof(TA);
     const char *Bg = reinterpret_cast<const char *>(Bt) + (long)col0 * K * sizeof(TA);
-    long ldb = (long)K * sizeof(TA);
-    uint4 ra[2], rb[2];
-    auto gload = [&](int kt) {
-        for (int r = 0; r < 2; r++) {
-            ra[r] = *reinterpret_cast<const uint4 *>(Ag + lr[r] * ldb + kt * 128 + lc[r] * 16);
-            rb[r] = *reinterpret_cast<const uint4 *>(Bg + lr[r] * ldb + kt * 128 + lc[r] * 16);
-        }
-    };
-    auto sstore = [&](int buf) {
-        for (int r = 0; r < 2; r++) {
-            *reinterpret_cast<uint4 *>(&As[buf][lr[r] * ROWB + lc[r] * 16]) = ra[r];
-            *reinterpret_cast<uint4 *>(&Bs[buf][lr[r] * ROWB + lc[r] * 16]) = rb[r];
-        }
-    };
-    accv acc[2][2];
-    for (int a = 0; a < 2; a++)
-        for (int b = 0; b < 2; b++) acc[a][b] = accv{0, 0, 0, 0};
+    long ld = (long)K * sizeof(TA);
+    // register staging of the next stage (all indices compile-time)
+    Stage<LA> ra;
+    Stage<LB> rb;
+    accv acc[TM][TN];
+#pragma unroll
+    for (int a = 0; a < TM; a++)
+#pragma unroll
+        for (int b = 0; b < TN; b++) acc[a][b] = accv{0, 0, 0, 0};
 
     int KT = K / BK;
-    gload(0);
-    sstore(0);
+    ra.load(Ag, ld, 0, tid);
+    rb.load(Bg, ld, 0, tid);
+    ra.store(As[0], tid);
+    rb.store(Bs[0], tid);
     __syncthreads();
     for (int kt = 0; kt < KT; kt++) {
         int buf = kt & 1;
-        if (kt + 1 < KT) gload(kt + 1);
+        if (kt + 1 < KT) {
+            ra.load(Ag, ld, kt + 1, tid);
+            rb.load(Bg, ld, kt + 1, tid);
+        }
 #pragma unroll
         for (int kg = 0; kg < 2; kg++) {
             int off = kg * 64 + q * 16;   // bytes: group kg of 4*VEC elements, lane group q
-            uint4 fa[2], fb[2];
-            for (int t = 0; t < 2; t++) {
-                fa[t] = *reinterpret_cast<const uint4 *>(&As[buf][(wr * 32 + t * 16 + m) * ROWB + off]);
-                fb[t] = *reinterpret_cast<const uint4 *>(&Bs[buf][(wc * 32 + t * 16 + m) * ROWB + off]);
-            }
-            for (int a = 0; a < 2; a++)
-                for (int b = 0; b < 2; b++) mfma_any<TA>(fa[a], fb[b], acc[a][b]);
+            u4v fa[TM], fb[TN];
+#pragma unroll
+            for (int t = 0; t < TM; t++)
+                fa[t] = *reinterpret_cast<const u4v *>(&As[buf][(wr * 16 * TM + t * 16 + m) * ROWB + off]);
+#pragma unroll
+            for (int t = 0; t < TN; t++)
+                fb[t] = *reinterpret_cast<const u4v *>(&Bs[buf][(wc * 16 * TN + t * 16 + m) * ROWB + off]);
+#pragma unroll
+            for (int a = 0; a < TM; a++)
+#pragma unroll
+                for (int b = 0; b < TN; b++) mfma_any<TA>(fa[a], fb[b], acc[a][b]);
         }
-        if (kt + 1 < KT) sstore(buf ^ 1);
+        if (kt + 1 < KT) {
+            ra.store(As[buf ^ 1], tid);
+            rb.store(Bs[buf ^ 1], tid);
+        }
         __syncthreads();
     }
-    (void)VEC;
 
-    // epilogue: acc[a][b][i] is C[row][col] with col = wc*32 + b*16 + m and
-    // row = wr*32 + a*16 + r, where r = 4q + i for the FP32-accumulating
+    // epilogue: acc[a][b][i] is C[row][col] with col = wc*16TN + b*16 + m and
+    // row = wr*16TM + a*16 + r, where r = 4q + i for the FP32-accumulating
     // instructions and r = 4i + q for v_mfma_f64_16x16x4f64 (lane layouts
     // measured on gfx950)
     const TR *bias = (const TR *)e.bias;
     constexpr bool kF64 = std::is_same<TA, double>::value;
-    for (int a = 0; a < 2; a++)
-        for (int b = 0; b < 2; b++)
+#pragma unroll
+    for (int a = 0; a < TM; a++)
+#pragma unroll
+        for (int b = 0; b < TN; b++)
+#pragma unroll
             for (int i = 0; i < 4; i++) {
-                int gm = row0 + wr * 32 + a * 16 + (kF64 ? 4 * i + q : 4 * q + i);
-                int gn = col0 + wc * 32 + b * 16 + m;
+                int gm = row0 + wr * 16 * TM + a * 16 + (kF64 ? 4 * i + q : 4 * q + i);
+                int gn = col0 + wc * 16 * TN + b * 16 + m;
                 if (gm >= M) continue;
                 long idx = (long)gm * N + gn;
                 TR v = (TR)acc[a][b][i];
@@ -217,27 +259,50 @@ __global__ void __launch_bounds__(256) k_energy(int n, const TR *__restrict__ y2
 }
 
 // dT[k][c] = sum_{a<M<} dD[a][c] T[k][a] + [c<M<] sum_b dD[c][b] T[k][b]
-// (D[a][b] = sum_k T[k][a] T[k][b]); one wave per atom.
+// (D[a][b] = sum_k T[k][a] T[k][b]); one wave per atom.  The atom's dD
+// (M< x M) and T (4 x M) are staged in LDS with rows padded by one element,
+// so the row-wise dot products of the second term are free of bank
+// conflicts; every lane then does the same amount of work.
 template <typename TR>
 __global__ void __launch_bounds__(256) k_dT(int n, const TR *__restrict__ dD, const TR *__restrict__ T,
                                             TR *__restrict__ dT)
 {
-    __shared__ TR Ts[4][4 * kM];
+    constexpr int P = kM + 1;   // padded row pitch
+    __shared__ TR sD[4][kMlt * P];
+    __shared__ TR sT[4][4 * P];
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int i = blockIdx.x * 4 + wave;
-    if (i < n)
-        for (int o = lane; o < 4 * kM; o += 64) Ts[wave][o] = T[(long)i * 4 * kM + o];
+    bool live = i < n;
+    if (live) {
+        const TR *dd = dD + (long)i * kDdim;
+        for (int o = lane; o < kDdim; o += 64) sD[wave][(o >> 7) * P + (o & (kM - 1))] = dd[o];
+        const TR *tt = T + (long)i * 4 * kM;
+        for (int o = lane; o < 4 * kM; o += 64) sT[wave][(o >> 7) * P + (o & (kM - 1))] = tt[o];
+    }
     __syncthreads();
-    if (i >= n) return;
-    const TR *dd = dD + (long)i * kDdim;
-    const TR *Tw = Ts[wave];
-    for (int o = lane; o < 4 * kM; o += 64) {
-        int k = o >> 7, c = o & (kM - 1);
-        TR v = 0;
-        for (int a = 0; a < kMlt; a++) v += dd[a * kM + c] * Tw[k * kM + a];
-        if (c < kMlt)
-            for (int b = 0; b < kM; b++) v += dd[c * kM + b] * Tw[k * kM + b];
-        dT[(long)i * 4 * kM + o] = v;
+    if (!live) return;
+    const TR *D = sD[wave], *Tw = sT[wave];
+    // first term: lane owns columns c = lane and lane + 64, all four k
+    TR acc[4][2];
+    for (int k = 0; k < 4; k++) acc[k][0] = acc[k][1] = 0;
+    for (int a = 0; a < kMlt; a++) {
+        TR d0 = D[a * P + lane], d1 = D[a * P + lane + 64];
+        for (int k = 0; k < 4; k++) {
+            TR t = Tw[k * P + a];
+            acc[k][0] += d0 * t;
+            acc[k][1] += d1 * t;
+        }
+    }
+    // second term: lane owns (c, k) = (lane / 4, lane % 4), c < M<
+    int c2 = lane >> 2, k2 = lane & 3;
+    TR s2 = 0;
+    for (int b = 0; b < kM; b++) s2 += D[c2 * P + b] * Tw[k2 * P + b];
+    TR *out = dT + (long)i * 4 * kM;
+    for (int k = 0; k < 4; k++) {
+        out[k * kM + lane + 64] = acc[k][1];
+        // columns < M< also receive the second term (held by lane 4c + k)
+        TR extra = __shfl(s2, (lane & 15) * 4 + k);
+        out[k * kM + lane] = acc[k][0] + (lane < kMlt ? extra : (TR)0);
     }
 }
 
@@ -322,19 +387,30 @@ __global__ void k_fill_zero_u32(unsigned *p, long n)
 }  // namespace
 
 // ----------------------------------------------------------- launchers
+template <typename TA, typename TR, int TM, int TN>
+static void launch_gemm_t(int epi, int M, int N, int K, const TA *A, const TA *Bt, const Epi &e, hipStream_t st)
+{
+    constexpr int BM = 32 * TM, BN = 32 * TN;
+    int ntiles = (N / BN) * div_up(M, BM);
+    dim3 grid(8 * div_up(ntiles, 8));
+    switch (epi) {
+    case EPI_LIN: hipLaunchKernelGGL((k_gemm_nt<TA, TR, EPI_LIN, TM, TN>), grid, dim3(256), 0, st, M, N, K, A, Bt, e); break;
+    case EPI_T1: hipLaunchKernelGGL((k_gemm_nt<TA, TR, EPI_T1, TM, TN>), grid, dim3(256), 0, st, M, N, K, A, Bt, e); break;
+    case EPI_T2: hipLaunchKernelGGL((k_gemm_nt<TA, TR, EPI_T2, TM, TN>), grid, dim3(256), 0, st, M, N, K, A, Bt, e); break;
+    case EPI_T3: hipLaunchKernelGGL((k_gemm_nt<TA, TR, EPI_T3, TM, TN>), grid, dim3(256), 0, st, M, N, K, A, Bt, e); break;
+    case EPI_EMB: hipLaunchKernelGGL((k_gemm_nt<TA, TR, EPI_EMB, TM, TN>), grid, dim3(256), 0, st, M, N, K, A, Bt, e); break;
+    case EPI_FOLD: hipLaunchKernelGGL((k_gemm_nt<TA, TR, EPI_FOLD, TM, TN>), grid, dim3(256), 0, st, M, N, K, A, Bt, e); break;
+    default: hipLaunchKernelGGL((k_gemm_nt<TA, TR, EPI_BWD, TM, TN>), grid, dim3(256), 0, st, M, N, K, A, Bt, e); break;
+    }
+}
+
+// Tile choice: 128 x 128 when M and N allow it (M padded to 128 rows), else
+// 64 x 64.
 template <typename TA, typename TR>
 void launch_gemm(int epi, int M, int N, int K, const TA *A, const TA *Bt, const Epi &e, hipStream_t st)
 {
-    dim3 grid(N / BN, div_up(M, BM));
-    switch (epi) {
-    case EPI_LIN: hipLaunchKernelGGL((k_gemm_nt<TA, TR, EPI_LIN>), grid, dim3(256), 0, st, M, N, K, A, Bt, e); break;
-    case EPI_T1: hipLaunchKernelGGL((k_gemm_nt<TA, TR, EPI_T1>), grid, dim3(256), 0, st, M, N, K, A, Bt, e); break;
-    case EPI_T2: hipLaunchKernelGGL((k_gemm_nt<TA, TR, EPI_T2>), grid, dim3(256), 0, st, M, N, K, A, Bt, e); break;
-    case EPI_T3: hipLaunchKernelGGL((k_gemm_nt<TA, TR, EPI_T3>), grid, dim3(256), 0, st, M, N, K, A, Bt, e); break;
-    case EPI_EMB: hipLaunchKernelGGL((k_gemm_nt<TA, TR, EPI_EMB>), grid, dim3(256), 0, st, M, N, K, A, Bt, e); break;
-    case EPI_FOLD: hipLaunchKernelGGL((k_gemm_nt<TA, TR, EPI_FOLD>), grid, dim3(256), 0, st, M, N, K, A, Bt, e); break;
-    default: hipLaunchKernelGGL((k_gemm_nt<TA, TR, EPI_BWD>), grid, dim3(256), 0, st, M, N, K, A, Bt, e); break;
-    }
+    if (N % 128 == 0 && M % 128 == 0) launch_gemm_t<TA, TR, 4, 4>(epi, M, N, K, A, Bt, e, st);
+    else launch_gemm_t<TA, TR, 2, 2>(epi, M, N, K, A, Bt, e, st);
 }
 template void launch_gemm<double, double>(int, int, int, int, const double *, const double *, const Epi &, hipStream_t);
 template void launch_gemm<float, float>(int, int, int, int, const float *, const float *, const Epi &, hipStream_t);

@@ -97,7 +97,7 @@ __device__ void bitonic_sort(unsigned long long *keys, int P)
 }
 
 __device__ void finish_atom(int i, int cnt, int cap, unsigned long long *keys, const int *wrap,
-                            int ki_packed, int *out_cnt, int *out_nei, int *out_shift, int *flags)
+                            int ki_packed, int *out_cnt, int *out_nei, int *out_shift, int *flags, int joff)
 {
     int lane = threadIdx.x;
     if (cnt > cap) {
@@ -120,7 +120,7 @@ __device__ void finish_atom(int i, int cnt, int cap, unsigned long long *keys, c
         int kj = wrap ? wrap[j] : 0;
         int kjx = (int)(signed char)(kj & 0xFF), kjy = (int)(signed char)((kj >> 8) & 0xFF),
             kjz = (int)(signed char)((kj >> 16) & 0xFF);
-        out_nei[(long)i * cap + t] = j;
+        out_nei[(long)i * cap + t] = j + joff;
         out_shift[(long)i * cap + t] = pack_shift(sx + kix - kjx, sy + kiy - kjy, sz + kiz - kjz);
     }
     if (lane == 0) out_cnt[i] = cnt;
@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(64) k_candidates_cells(
     double Lz, int ncx, int ncy, int ncz, int Rx, int Ry, int Rz, int cellcap,
     const int *__restrict__ cell_cnt, const int *__restrict__ cell_atoms, double rcs2, int cap,
     int *__restrict__ out_cnt, int *__restrict__ out_nei, int *__restrict__ out_shift,
-    int *__restrict__ flags)
+    int *__restrict__ flags, int joff)
 {
     HIP_DYNAMIC_SHARED(unsigned long long, keys)
     __shared__ int count;
@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(64) k_candidates_cells(
         }
     }
     __syncthreads();
-    finish_atom(i, count, cap, keys, wrap, wrap[i], out_cnt, out_nei, out_shift, flags);
+    finish_atom(i, count, cap, keys, wrap, wrap[i], out_cnt, out_nei, out_shift, flags, joff);
 }
 
 // Open boundary: brute force over all atoms (for clusters of modest size).
@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(64) k_candidates_open(int n, const double *__r
                                                         int cap, int *__restrict__ out_cnt,
                                                         int *__restrict__ out_nei,
                                                         int *__restrict__ out_shift,
-                                                        int *__restrict__ flags)
+                                                        int *__restrict__ flags, int joff)
 {
     HIP_DYNAMIC_SHARED(unsigned long long, keys)
     __shared__ int count;
@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(64) k_candidates_open(int n, const double *__r
         }
     }
     __syncthreads();
-    finish_atom(i, count, cap, keys, nullptr, 0, out_cnt, out_nei, out_shift, flags);
+    finish_atom(i, count, cap, keys, nullptr, 0, out_cnt, out_nei, out_shift, flags, joff);
 }
 
 }  // namespace
@@ -224,7 +224,7 @@ dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, c
     if (reset_flags) launch_fill_zero_int(nl->flags, kNumFlags, st);
     if (!nl->periodic) {
         hipLaunchKernelGGL(k_candidates_open, dim3(n), dim3(64), lds, st, n, x, types, rcs2, nl->cap,
-                           nl->cnt, nl->nei, nl->shift, nl->flags);
+                           nl->cnt, nl->nei, nl->shift, nl->flags, 0);
         return DP_OK;
     }
     long ncell = (long)nl->nc[0] * nl->nc[1] * nl->nc[2];
@@ -243,8 +243,93 @@ dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, c
                        nl->wpos, nl->wrap, nl->L[0], nl->L[1],
                        nl->L[2], nl->nc[0], nl->nc[1], nl->nc[2], R[0], R[1], R[2], nl->cellcap,
                        nl->cell_cnt, nl->cell_atoms, rcs2, nl->cap, nl->cnt, nl->nei, nl->shift,
-                       nl->flags);
+                       nl->flags, 0);
     return DP_OK;
+}
+
+dp_status launch_build_nlist_range(dp_nlist *nl, const double *x, int off, int n, const double *L,
+                                   hipStream_t st)
+{
+    double rcs = nl->rc_build, rcs2 = rcs * rcs;
+    int cap2 = 1;
+    while (cap2 < nl->cap) cap2 <<= 1;
+    size_t lds = sizeof(unsigned long long) * cap2;
+    long cap = nl->cap;
+    const double *xr = x + 3L * off;
+    int *cnt = nl->cnt + off, *nei = nl->nei + off * cap, *shift = nl->shift + off * cap;
+    if (!L) {
+        hipLaunchKernelGGL(k_candidates_open, dim3(n), dim3(64), lds, st, n, xr, (const int *)nullptr, rcs2,
+                           nl->cap, cnt, nei, shift, nl->flags, off);
+        return DP_OK;
+    }
+    int nc[3], R[3];
+    for (int a = 0; a < 3; a++) {
+        nc[a] = (int)floor(L[a] / (0.5 * rcs));
+        if (nc[a] < 1) nc[a] = 1;
+        R[a] = (int)ceil(rcs / (L[a] / nc[a]) - 1e-12);
+        if (R[a] > 2) return fail(DP_ERR_UNSUPPORTED, "box edge shorter than (rcut + skin) / 2");
+    }
+    long ncell = (long)nc[0] * nc[1] * nc[2];
+    if ((size_t)(ncell * nl->cellcap) > nl->ncell_alloc) return fail(DP_ERR_STATE, "cell grid too small");
+    launch_fill_zero_int(nl->cell_cnt, ncell, st);
+    hipLaunchKernelGGL(k_bin, dim3(div_up(n, 256)), dim3(256), 0, st, n, xr, (const int *)nullptr, L[0], L[1], L[2],
+                       nc[0], nc[1], nc[2], nl->cellcap, nl->wpos + 3L * off, nl->wrap + off, nl->cell_cnt,
+                       nl->cell_atoms, nl->flags);
+    hipLaunchKernelGGL(k_candidates_cells, dim3(n), dim3(64), lds, st, n, nl->wpos + 3L * off, nl->wrap + off, L[0],
+                       L[1], L[2], nc[0], nc[1], nc[2], R[0], R[1], R[2], nl->cellcap, nl->cell_cnt, nl->cell_atoms,
+                       rcs2, nl->cap, cnt, nei, shift, nl->flags, off);
+    return DP_OK;
+}
+
+namespace {
+
+// Expands per-request box edges to per-atom ones; one block per request.
+__global__ void k_expand_boxes(const int *__restrict__ off, const double *__restrict__ Lreq,
+                               double *__restrict__ atomL)
+{
+    int r = blockIdx.x;
+    for (int i = off[r] + threadIdx.x; i < off[r + 1]; i += blockDim.x)
+        for (int a = 0; a < 3; a++) atomL[3L * i + a] = Lreq[3 * r + a];
+}
+
+// Per request (block): E = sum of E_i and W = sum of W_i over its atoms, in
+// an order fixed relative to the request's first atom (so the result does
+// not depend on where the request sits in the batch).
+__global__ void __launch_bounds__(256) k_segment_reduce(const int *__restrict__ off,
+                                                        const double *__restrict__ e_atom,
+                                                        const double *__restrict__ w_atom,
+                                                        double *__restrict__ energy, double *__restrict__ virial)
+{
+    __shared__ double sh[256][10];
+    int r = blockIdx.x, t = threadIdx.x;
+    double v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i = off[r] + t; i < off[r + 1]; i += 256) {
+        v[0] += e_atom[i];
+        if (w_atom)
+            for (int q = 0; q < 9; q++) v[1 + q] += w_atom[9L * i + q];
+    }
+    for (int q = 0; q < 10; q++) sh[t][q] = v[q];
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+        if (t < s2)
+            for (int q = 0; q < 10; q++) sh[t][q] += sh[t + s2][q];
+        __syncthreads();
+    }
+    if (t == 0 && energy) energy[r] = sh[0][0];
+    if (t < 9 && virial && w_atom) virial[9 * r + t] = sh[0][1 + t];
+}
+
+}  // namespace
+
+void launch_segment_reduce(int nreq, const int *offsets, const double *e_atom, const double *w_atom,
+                           double *energy, double *virial, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_segment_reduce, dim3(nreq), dim3(256), 0, st, offsets, e_atom, w_atom, energy, virial);
+}
+
+void launch_expand_boxes(int nreq, const int *offsets, const double *Lreq, double *atomL, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_expand_boxes, dim3(nreq), dim3(256), 0, st, offsets, Lreq, atomL);
 }
 
 }  // namespace dp

@@ -253,3 +253,23 @@ def test_cu108k_sampled(P, model, cu_cfg, cu_params, otab, precision):
     assert abs(float(np.sum(got["F"][:, 0]))) < 1e-8 * math.sqrt(len(x))
     st = nl.stats()
     assert st["table_oob"] == 0 and st["cap_overflow"] == 0
+
+
+@pytest.mark.parametrize("precision", [2, 1])
+def test_cu1m_mixed_sampled(P, model, cu_cfg, cu_params, otab, precision):
+    """1,048,576-atom copper (64^3 cells, sigma 0.08 A), mixed BF16 and FP32:
+    sampled per-atom energies and forces against the FP64 oracle."""
+    x, box = synth.copper(64, 0.08, synth.SEED_CFG[3])
+    got, nl = run(P, model, x, box, precision)
+    rng = np.random.default_rng(3)
+    e_idx = rng.choice(len(x), 64, replace=False)
+    f_idx = rng.choice(len(x), 8, replace=False)
+    e_ref, F_ref = sampled_reference(cu_cfg, cu_params, otab, x, box, e_idx, f_idx)
+    dEi = np.max(np.abs(got["e_atom"][e_idx] - e_ref))
+    eF = np.sqrt(np.mean((got["F"][f_idx] - F_ref) ** 2))
+    Fs = np.sqrt(np.mean(F_ref ** 2))
+    print(f"1M prec={precision} max dE_i={dEi:.3g} RMSE_F={eF:.3g} (F_rms {Fs:.3g})")
+    assert dEi <= (1e-4 if precision == 2 else 1e-5)
+    assert eF <= 1e-3 and eF <= (1e-3 if precision == 2 else 1e-4) * Fs
+    st = nl.stats()
+    assert st["table_oob"] == 0 and st["cap_overflow"] == 0
