@@ -30,7 +30,32 @@ PEAK = {  # MI355X published peaks, TFLOP/s (dense)
     ("mfma", "f32"): 157.3, ("mfma", "f64"): 78.6, ("mfma", "bf16"): 2500.0,
 }
 HBM_PEAK_GBS = 8000.0
-FIT_FLOP_PER_ATOM = 2 * (2048 * 240 + 240 * 240 * 2)   # one pass (fwd or input-grad)
+COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters.json")
+
+
+def _kernel_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("emb.hip", "env.h", "emb_common.h", "fit.hip"):
+        with open(os.path.join(ROOT, "paper_2201_01446_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, dt):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's
+    reading for an elementwise kernel of known size), or None when there is
+    none or the kernel sources changed after it was taken."""
+    try:
+        with open(COUNTERS) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    k = rec.get("kernels", {}).get(f"{kernel}_{dt}")
+    if k is None or rec.get("sources_digest") != _kernel_sources_digest():
+        return None
+    return round(k["fetch_kib"] * rec["fetch_scale"] * 1024 + k["write_kib"] * rec["write_scale"] * 1024)
 
 
 def parse():
@@ -46,6 +71,9 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one elementwise negation over this many MiB (reads and writes it once): "
+                         "the calibration of HBM byte counters")
     return ap.parse_args()
 
 
@@ -86,6 +114,12 @@ def main():
     import paper_2201_01446_amd as P
     import synth
 
+    if args.copy_probe_mib:
+        a = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.neg(a, out=b)
+        torch.cuda.synchronize()
+        del a, b
     cfg = synth.copper_model_config()
     params = synth.model_params(cfg)
     model = P.Model(cfg, params).tabulate(0.7, 0.01, 1.5, 0.1)
@@ -107,29 +141,46 @@ def main():
     # neighbor statistics of the final configuration (for the FLOP counts)
     d = P.descriptor(model, res32["nl"], res32["x"], precision=P.FP32)
     sum_nei = int(d["nnei"].sum().item())
+    sum_seg = int(d["nseg"].sum().item())
 
-    def roofline(res, dt):
+    def roofline(res, dt, rs):
+        """Per-kernel algorithmic work per launch and the dominant kernel's
+        roofline (the kernel with the largest time per step)."""
         kern = res["kernels"]
-        steps = K
-        flops = {
-            "emb_fwd": (sum_nei * 128 * 9 * 2, "alu"),
-            "emb_bwd": (sum_nei * 128 * 18 * 2, "alu"),
-            "fit_gemm": (N * FIT_FLOP_PER_ATOM * 2, "mfma"),
+        fit_in = N * 2.0 * 240 * 2048          # 2048 -> 240 (and its transpose)
+        fit_hid = N * 2.0 * 240 * 240          # 240 -> 240
+        # embedding kernels in the interval-moment form they execute (FMA = 2 FLOP):
+        # forward 24 moments per neighbor, 24 per (segment, column), D 16 x 128 x 4;
+        # backward dE/dT 2 x 16 x 128 x 4, 24 per (segment, column), 40 per neighbor
+        work = {   # name: (work per launch, bound)
+            "emb_fwd": (2.0 * (24 * sum_nei + 24 * 128 * sum_seg + 8192 * N), "alu"),
+            "emb_bwd": (2.0 * (16384 * N + 24 * 128 * sum_seg + 40 * sum_nei), "alu"),
+            "fit_fwd1": (fit_in, "mfma"), "fit_bwd1": (fit_in, "mfma"),
+            "fit_fwd2": (fit_hid, "mfma"), "fit_fwd3": (fit_hid, "mfma"),
+            "fit_bwd3": (fit_hid, "mfma"), "fit_bwd2": (fit_hid, "mfma"),
+            "dT": (N * 3072.0 * rs, "hbm"),      # read dD (2048) and T (512), write dT (512)
         }
-        per = {}
+        table = {}
         for name, (tot_ms, cnt) in kern.items():
-            per[name] = dict(avg_ms=tot_ms / max(cnt, 1), launches=cnt, total_ms=tot_ms)
-        dom = max((n for n in per if n in flops), key=lambda n: per[n]["total_ms"])
-        fl, bound = flops[dom]
-        launches_per_step = per[dom]["launches"] / steps
-        per_launch = fl / launches_per_step
-        achieved = per_launch / (per[dom]["avg_ms"] * 1e-3) / 1e12
-        peak = PEAK[(bound, dt)]
-        return dom, dict(bound=bound, achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
-                         frac=round(achieved / peak, 4), traffic=None, kernel=dom,
-                         per_launch_flop=per_launch), per
+            avg = tot_ms / max(cnt, 1)
+            row = dict(avg_ms=round(avg, 4), launches_per_step=round(cnt / K, 3))
+            if name in work:
+                w, bound = work[name]
+                if bound == "hbm":
+                    ach, peak, unit = w / (avg * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s"
+                else:
+                    ach, peak, unit = w / (avg * 1e-3) / 1e12, PEAK[(bound, dt)], "TFLOP/s"
+                row.update(bound=bound, achieved=round(ach, 3), peak=peak, unit=unit, frac=round(ach / peak, 4))
+            table[name] = row
+        dom = max((n for n in table if "frac" in table[n]),
+                  key=lambda n: table[n]["avg_ms"] * table[n]["launches_per_step"])
+        t = table[dom]
+        roof = dict(bound=t["bound"], achieved=t["achieved"], peak=t["peak"], unit=t["unit"], frac=t["frac"],
+                    traffic=measured_traffic(dom, dt), kernel=dom, per_launch_work=work[dom][0],
+                    avg_ms=t["avg_ms"])
+        return dom, roof, table
 
-    dom, roof, per32 = roofline(res32, "f32")
+    dom, roof, per32 = roofline(res32, "f32", 4)
     value = N * K / (res32["ms"] * 1e-3)
     ms_step = res32["ms"] / K
 
@@ -159,15 +210,16 @@ def main():
                    "natoms": N, "precision": "fp32", "mode": "compressed"},
         "ns_per_day": round(value / N * 86400 * 1e-6, 3),
         "roofline": roof,
-        "kernels_fp32": {k: round(v["avg_ms"], 4) for k, v in per32.items()},
+        "kernels_fp32": per32,
         "energy_drift_fp32_eV_per_atom": float((etot[-1] - etot[0]) / N),
         "mean_neighbors": sum_nei / N,
+        "mean_interval_segments": sum_seg / N,
     }
     if res64 is not None:
         v64 = N * K / (res64["ms"] * 1e-3)
-        _, roof64, per64 = roofline(res64, "f64")
+        _, roof64, per64 = roofline(res64, "f64", 8)
         out["fp64"] = {"value": round(v64, 1), "ms_per_step": round(res64["ms"] / K, 4),
-                       "roofline": roof64, "kernels": {k: round(v["avg_ms"], 4) for k, v in per64.items()}}
+                       "roofline": roof64, "kernels": per64}
     vbf = N * K / (resbf["ms"] * 1e-3)
     out["mixed_bf16"] = {"value": round(vbf, 1), "ms_per_step": round(resbf["ms"] / K, 4),
                          "kernels": {k: round(v[0] / max(v[1], 1), 4) for k, v in resbf["kernels"].items()}}

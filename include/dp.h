@@ -158,12 +158,15 @@ dp_status dp_energy_backward(dp_model *model, dp_nlist *nlist, int natoms, const
                              void *stream);
 
 /* Intermediate results for testing: per atom the number of neighbors used
- * (nnei_d, int32), T = desc_scale * R^T G (T_d, natoms x 4 x M, row k of
- * the 4 environment columns) and D = (T<)^T T (D_d, natoms x M< x M), all
- * FP64 copies; any may be NULL. */
+ * (nnei_d, int32), the number of runs of equal table interval in its
+ * distance-sorted neighbor list (nseg_d, int32; compressed mode only, the
+ * work unit of the kernels' interval-moment contraction; left untouched in
+ * plain mode), T = desc_scale * R^T G (T_d, natoms x 4 x M, row k of the 4
+ * environment columns) and D = (T<)^T T (D_d, natoms x M< x M), all FP64
+ * copies; any may be NULL. */
 dp_status dp_descriptor(dp_model *model, dp_nlist *nlist, int natoms, const double *coords_d,
-                        const double *box_h, int mode, int precision, int *nnei_d, double *T_d,
-                        double *D_d, void *stream);
+                        const double *box_h, int mode, int precision, int *nnei_d, int *nseg_d,
+                        double *T_d, double *D_d, void *stream);
 
 /* Sticky counters of the list since its last build (synchronises):
  * max_nei: most neighbors within rcut seen for one atom; n_sel_overflow:

@@ -126,16 +126,18 @@ def compute(model, nlist, coords, mode=COMPRESSED, precision=FP64, forces=True, 
 
 
 def descriptor(model, nlist, coords, mode=COMPRESSED, precision=FP64):
-    """Per-atom neighbor count, T (N,4,M) and D (N, M<*M) as float64 tensors."""
+    """Per-atom neighbor count, interval-run count (compressed mode; zeros
+    in plain mode), T (N,4,M) and D (N, M<*M) as float64 tensors."""
     n = coords.shape[0]
     M, Ml = model.cfg["emb"][2], model.cfg["m_lt"]
     dev = coords.device
     nn = torch.empty(n, dtype=torch.int32, device=dev)
+    ns = torch.zeros(n, dtype=torch.int32, device=dev)
     T = torch.empty((n, 4, M), dtype=torch.float64, device=dev)
     D = torch.empty((n, Ml * M), dtype=torch.float64, device=dev)
-    check(lib.dp_descriptor(model.h, nlist.h, n, _ptr(coords), None, mode, precision, _ptr(nn), _ptr(T), _ptr(D),
-                            _stream()))
-    return dict(nnei=nn, T=T, D=D)
+    check(lib.dp_descriptor(model.h, nlist.h, n, _ptr(coords), None, mode, precision, _ptr(nn), _ptr(ns), _ptr(T),
+                            _ptr(D), _stream()))
+    return dict(nnei=nn, nseg=ns, T=T, D=D)
 
 
 def nve_run(model, nlist, x, v, box, mass, dt, nsteps, rebuild_every=10, skin=2.0, mode=COMPRESSED,

@@ -136,7 +136,7 @@ bool box_ok(const double *box, double L[3])
 void free_nlist_arrays(dp_nlist *nl)
 {
     void *p[] = {nl->cell_cnt, nl->cell_atoms, nl->wpos, nl->wrap, nl->cnt, nl->nei, nl->shift,
-                 nl->flags, nl->ws, nl->ws_plain, nl->force_tmp, nl->scal};
+                 nl->dist, nl->rev, nl->pg, nl->flags, nl->ws, nl->ws_plain, nl->force_tmp, nl->scal};
     for (void *q : p)
         if (q) (void)hipFree(q);
 }
@@ -206,7 +206,7 @@ dp_status prepare_nlist(const dp_model *m, int natoms, const double *box, double
     if (grow) {
         int alloc = natoms > nl->alloc_atoms ? natoms : nl->alloc_atoms;
         int capn = cap > nl->cap ? cap : nl->cap;
-        void *p[] = {nl->wpos, nl->wrap, nl->cnt, nl->nei, nl->shift, nl->force_tmp};
+        void *p[] = {nl->wpos, nl->wrap, nl->cnt, nl->nei, nl->shift, nl->dist, nl->rev, nl->pg, nl->force_tmp};
         for (void *q : p)
             if (q) DP_HIP(hipFree(q));
         DP_HIP(hipMalloc(&nl->wpos, sizeof(double) * 3 * (size_t)alloc));
@@ -214,6 +214,9 @@ dp_status prepare_nlist(const dp_model *m, int natoms, const double *box, double
         DP_HIP(hipMalloc(&nl->cnt, sizeof(int) * (size_t)alloc));
         DP_HIP(hipMalloc(&nl->nei, sizeof(int) * (size_t)alloc * capn));
         DP_HIP(hipMalloc(&nl->shift, sizeof(int) * (size_t)alloc * capn));
+        DP_HIP(hipMalloc(&nl->dist, sizeof(float) * (size_t)alloc * capn));
+        DP_HIP(hipMalloc(&nl->rev, sizeof(short) * (size_t)alloc * capn));
+        DP_HIP(hipMalloc(&nl->pg, sizeof(double) * 3 * (size_t)alloc * capn));
         DP_HIP(hipMalloc(&nl->force_tmp, sizeof(double) * 3 * (size_t)alloc));
         nl->alloc_atoms = alloc;
         nl->cap = capn;
@@ -225,7 +228,7 @@ dp_status prepare_nlist(const dp_model *m, int natoms, const double *box, double
     }
     if (!nl->scal) DP_HIP(hipMalloc(&nl->scal, sizeof(double) * 512));
     nl->natoms = natoms;
-    dp_status s = ensure_ws(nl, DP_FP64);
+    dp_status s = ensure_ws(nl, DP_FP64, m->cfg.sel);
     if (s != DP_OK) return s;
     *inout = nl;
     return DP_OK;
@@ -462,13 +465,13 @@ dp_status dp_nlist_destroy(dp_nlist *nl)
 
 static dp_status compute_common(dp_model *m, dp_nlist *nl, int natoms, const double *x, int mode, int precision,
                                 double *energy, double *force, double *virial, double *atom_energy, int *nnei,
-                                double *T, double *D, hipStream_t st, int phase = 0)
+                                int *nseg, double *T, double *D, hipStream_t st, int phase = 0)
 {
     dp_status s = check_compute_args(m, nl, natoms, x, mode, precision);
     if (s != DP_OK) return s;
     if (phase == 2 && nl->fwd_token != precision + 1 + 8 * mode)
         return fail(DP_ERR_STATE, "no kept forward of this precision and mode on this list");
-    if ((s = ensure_ws(nl, precision)) != DP_OK) return s;
+    if ((s = ensure_ws(nl, precision, m->cfg.sel)) != DP_OK) return s;
     ComputeArgs a;
     a.m = m;
     a.nl = nl;
@@ -479,6 +482,7 @@ static dp_status compute_common(dp_model *m, dp_nlist *nl, int natoms, const dou
     a.virial = virial;
     a.atom_energy = atom_energy;
     a.nnei_out = nnei;
+    a.nseg_out = nseg;
     a.T_out = T;
     a.D_out = D;
     a.need_forces = force || virial;
@@ -502,14 +506,14 @@ dp_status dp_compute(dp_model *m, dp_nlist *nl, int natoms, const double *coords
         return fail(DP_ERR_ARG, "the list was built for an open cluster");
     }
     return compute_common(m, nl, natoms, coords_d, mode, precision, energy_d, force_d, virial_d, atom_energy_d,
-                          nullptr, nullptr, nullptr, (hipStream_t)stream);
+                          nullptr, nullptr, nullptr, nullptr, (hipStream_t)stream);
 }
 
 dp_status dp_energy_forward(dp_model *m, dp_nlist *nl, int natoms, const double *coords_d, int mode,
                             int precision, double *energy_d, double *atom_energy_d, void *stream)
 {
     return compute_common(m, nl, natoms, coords_d, mode, precision, energy_d, nullptr, nullptr, atom_energy_d,
-                          nullptr, nullptr, nullptr, (hipStream_t)stream, 1);
+                          nullptr, nullptr, nullptr, nullptr, (hipStream_t)stream, 1);
 }
 
 dp_status dp_energy_backward(dp_model *m, dp_nlist *nl, int natoms, const double *coords_d, int mode,
@@ -517,15 +521,15 @@ dp_status dp_energy_backward(dp_model *m, dp_nlist *nl, int natoms, const double
 {
     if (!force_d && !virial_d) return fail(DP_ERR_ARG, "nothing to compute");
     return compute_common(m, nl, natoms, coords_d, mode, precision, nullptr, force_d, virial_d, nullptr, nullptr,
-                          nullptr, nullptr, (hipStream_t)stream, 2);
+                          nullptr, nullptr, nullptr, (hipStream_t)stream, 2);
 }
 
 dp_status dp_descriptor(dp_model *m, dp_nlist *nl, int natoms, const double *coords_d, const double *box_h,
-                        int mode, int precision, int *nnei_d, double *T_d, double *D_d, void *stream)
+                        int mode, int precision, int *nnei_d, int *nseg_d, double *T_d, double *D_d, void *stream)
 {
     (void)box_h;
     return compute_common(m, nl, natoms, coords_d, mode, precision, nullptr, nullptr, nullptr, nullptr, nnei_d,
-                          T_d, D_d, (hipStream_t)stream);
+                          nseg_d, T_d, D_d, (hipStream_t)stream);
 }
 
 dp_status dp_nlist_stats(dp_nlist *nl, int *max_nei, int *n_sel_overflow, int *n_table_oob, int *n_cap_overflow)
@@ -557,7 +561,7 @@ dp_status dp_nve_run(dp_model *m, dp_nlist **nlp, int natoms, double *x, double 
     if ((s = step_check("build_nlist", st)) != DP_OK) return s;
     double *F = nl->force_tmp, *E = nl->scal, *part = nl->scal + 256;
     double kick = 0.5 * dt_fs * acc_unit() / mass, kef = 0.5 * mass * ke_unit();
-    s = compute_common(m, nl, natoms, x, mode, precision, E, F, nullptr, nullptr, nullptr, nullptr, nullptr, st);
+    s = compute_common(m, nl, natoms, x, mode, precision, E, F, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, st);
     if (s != DP_OK) return s;
     if (thermo) launch_thermo(v, E, natoms, kef, thermo, part, st);
     for (int step = 1; step <= nsteps; step++) {
@@ -567,7 +571,7 @@ dp_status dp_nve_run(dp_model *m, dp_nlist **nlp, int natoms, double *x, double 
             if (s != DP_OK) return s;
             if ((s = step_check("build_nlist", st)) != DP_OK) return s;
         }
-        s = compute_common(m, nl, natoms, x, mode, precision, E, F, nullptr, nullptr, nullptr, nullptr, nullptr, st);
+        s = compute_common(m, nl, natoms, x, mode, precision, E, F, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, st);
         if (s != DP_OK) return s;
         launch_verlet_kick(v, F, natoms, kick, st);
         if (thermo) launch_thermo(v, E, natoms, kef, thermo + 2 * step, part, st);
@@ -581,8 +585,10 @@ dp_status dp_nve_run(dp_model *m, dp_nlist **nlp, int natoms, double *x, double 
 dp_status dp_footprint_bytes(const dp_model *m, int natoms, size_t *bytes)
 {
     if (!m || natoms < 0 || !bytes) return fail(DP_ERR_ARG, "bad argument");
-    size_t per = (size_t)kCapMax * 8 + 3 * 8 + 3 * 8 + 4 * 4 + 3 * 8;   // candidates, positions, boxes, counts
-    size_t ws = std::max(ws_bytes_for_atoms(natoms, DP_FP64), ws_bytes_for_atoms(natoms, DP_MIXED_BF16));
+    // candidates (index, shift, distance, reverse slot, pair gradient), positions, boxes, counts
+    size_t per = (size_t)kCapMax * (4 + 4 + 4 + 2 + 24) + 3 * 8 + 3 * 8 + 4 * 4 + 3 * 8;
+    size_t ws = std::max(ws_bytes_for_atoms(natoms, DP_FP64, m->cfg.sel),
+                         ws_bytes_for_atoms(natoms, DP_MIXED_BF16, m->cfg.sel));
     *bytes = per * (size_t)natoms + ws;
     return DP_OK;
 }
@@ -608,6 +614,9 @@ dp_status dp_batch_create(dp_model *m, int max_atoms, int max_requests, double s
     DP_HIP(hipMalloc(&nl->cnt, sizeof(int) * A));
     DP_HIP(hipMalloc(&nl->nei, sizeof(int) * A * kCapMax));
     DP_HIP(hipMalloc(&nl->shift, sizeof(int) * A * kCapMax));
+    DP_HIP(hipMalloc(&nl->dist, sizeof(float) * A * kCapMax));
+    DP_HIP(hipMalloc(&nl->rev, sizeof(short) * A * kCapMax));
+    DP_HIP(hipMalloc(&nl->pg, sizeof(double) * 3 * A * kCapMax));
     DP_HIP(hipMalloc(&nl->force_tmp, sizeof(double) * 3 * A));
     DP_HIP(hipMalloc(&nl->atomL, sizeof(double) * 3 * A));
     DP_HIP(hipMalloc(&nl->flags, sizeof(int) * kNumFlags));
@@ -618,7 +627,7 @@ dp_status dp_batch_create(dp_model *m, int max_atoms, int max_requests, double s
     DP_HIP(hipHostMalloc((void **)&b->off_h, sizeof(int) * (max_requests + 1), hipHostMallocDefault));
     DP_HIP(hipHostMalloc((void **)&b->Lreq_h, sizeof(double) * 3 * max_requests, hipHostMallocDefault));
     DP_HIP(hipEventCreateWithFlags(&b->staged, hipEventDisableTiming));
-    dp_status s = ensure_ws(nl, DP_FP64);
+    dp_status s = ensure_ws(nl, DP_FP64, m->cfg.sel);
     if (s != DP_OK) return s;
     *out = b;
     return DP_OK;
@@ -711,6 +720,7 @@ dp_status dp_batch_compute(dp_model *m, dp_batch *b, int nreq, const dp_request 
         dp_status s = launch_build_nlist_range(nl, coords_d, reqs[r].offset, reqs[r].natoms, Lp, st);
         if (s != DP_OK) return s;
     }
+    launch_reverse(nl, 0, (int)total, st);
     dp_status s = step_check("batch_nlist", st);
     if (s != DP_OK) return s;
     nl->natoms = (int)total;

@@ -6,8 +6,9 @@
 //   3 x GEMM         fitting net forward (tanh / shortcut epilogues)
 //   k_energy         E_i, dz3
 //   3 x GEMM         fitting-net input gradient -> dD
-//   k_dT             dE/dT from dE/dD
-//   k_emb_bwd        adjoint of the fused step -> forces (atomics), W_i
+//   k_emb_bwd        dE/dT from dE/dD and T, then the adjoint of the fused
+//                    step -> F_i's own part, dE_i/dr_ij per candidate, W_i
+//   k_force_gather   F_j -= dE_i/dr_ij over the atoms i that list j
 //   k_reduce_*       deterministic FP64 sums of E_i and W_i
 // Buffers live in the neighbor list's workspace; rows are padded to 128 so
 // the GEMM tiles never read past an allocation.
@@ -22,6 +23,8 @@ namespace {
 
 struct WS {
     void *T, *D, *y1r, *y1o, *y2r, *y2o, *t2r, *t3r, *dz3o, *dy2r, *dz2o, *dz1o, *dDr, *dT;
+    void *rec;   // the forward's compacted neighbors (r_ij, j) per atom, sel slots
+    int *rcnt;   // their number per atom
     double *e_atom, *w_atom, *part;
 };
 
@@ -32,7 +35,7 @@ size_t sizes(int precision, size_t &rs, size_t &os)
     return 0;
 }
 
-size_t ws_bytes_for(int np, int precision)
+size_t ws_bytes_for(int np, int precision, int sel)
 {
     size_t rs, os;
     sizes(precision, rs, os);
@@ -45,11 +48,12 @@ size_t ws_bytes_for(int np, int precision)
     r += 5 * al(np * (size_t)kFitPad * os);   // y1o y2o dz3o dz2o dz1o
     r += al(np * (size_t)kDdim * rs);   // dD
     r += al(np * 4 * kM * rs);          // dT
+    r += al((size_t)np * sel * 4 * rs) + al(np * 4);   // neighbor records, counts
     r += al(np * 8) + al(np * 72) + al(256 * 10 * 8);
     return r;
 }
 
-WS carve(void *base, int np, int precision)
+WS carve(void *base, int np, int precision, int sel)
 {
     size_t rs, os;
     sizes(precision, rs, os);
@@ -75,6 +79,8 @@ WS carve(void *base, int np, int precision)
     w.dz1o = take(np * (size_t)kFitPad * os);
     w.dDr = take(np * (size_t)kDdim * rs);
     w.dT = take(np * 4 * kM * rs);
+    w.rec = take((size_t)np * sel * 4 * rs);
+    w.rcnt = (int *)take(np * 4);
     w.e_atom = (double *)take(np * 8);
     w.w_atom = (double *)take(np * 72);
     w.part = (double *)take(256 * 10 * 8);
@@ -101,17 +107,17 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
         if (PLAIN) {
             if ((s = plain_forward<TR, TA>(m, a.nl, n, a.x, w.T, w.D, a.nnei_out, st)) != DP_OK) return s;
         } else {
-            DP_TIMED("emb_fwd", st, launch_emb_fwd(m, a.nl, n, a.x, a.precision, w.T, w.D, a.nnei_out, st));
+            DP_TIMED("emb_fwd", st, launch_emb_fwd(m, a.nl, n, a.x, a.precision, w.T, w.D, w.rec, w.rcnt, a.nnei_out, a.nseg_out, st));
             if ((s = step_check("emb_fwd", st)) != DP_OK) return s;
         }
         if (a.T_out) launch_to_double<TR>((long)n * 4 * kM, (const TR *)w.T, a.T_out, st);
         if (a.D_out) launch_op_to_double<TA>(n, kDdim, (const TA *)w.D, a.D_out, st);
         e = Epi{c1, nullptr, nullptr, nullptr, w.y1r, w.y1o, nullptr};
-        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T1, mr, kFitPad, ks * kDdim, (const TA *)w.D, (const TA *)fw.V1t, e, st));
+        DP_TIMED("fit_fwd1", st, launch_gemm<TA, TR>(EPI_T1, mr, kFitPad, ks * kDdim, (const TA *)w.D, (const TA *)fw.V1t, e, st));
         e = Epi{c2, w.y1r, nullptr, nullptr, w.y2r, w.y2o, w.t2r};
-        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T2, mr, kFitPad, ks * kFitPad, (const TA *)w.y1o, (const TA *)fw.V2t, e, st));
+        DP_TIMED("fit_fwd2", st, launch_gemm<TA, TR>(EPI_T2, mr, kFitPad, ks * kFitPad, (const TA *)w.y1o, (const TA *)fw.V2t, e, st));
         e = Epi{c3, nullptr, nullptr, nullptr, nullptr, nullptr, w.t3r};
-        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_T3, mr, kFitPad, ks * kFitPad, (const TA *)w.y2o, (const TA *)fw.V3t, e, st));
+        DP_TIMED("fit_fwd3", st, launch_gemm<TA, TR>(EPI_T3, mr, kFitPad, ks * kFitPad, (const TA *)w.y2o, (const TA *)fw.V3t, e, st));
     }
     // E_i always; dz3 = w4 (1 - t3^2) when the backward follows
     launch_energy<TA, TR>(n, (const TR *)w.y2r, (const TR *)w.t3r, w4, a.m->b4, w.e_atom,
@@ -119,18 +125,20 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
     if ((s = step_check("fitting_forward", st)) != DP_OK) return s;
     if (bwd) {
         e = Epi{nullptr, nullptr, w4, w.t2r, w.dy2r, w.dz2o, nullptr};
-        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_BWD, mr, kFitPad, ks * kFitPad, (const TA *)w.dz3o, (const TA *)fw.V3, e, st));
+        DP_TIMED("fit_bwd3", st, launch_gemm<TA, TR>(EPI_BWD, mr, kFitPad, ks * kFitPad, (const TA *)w.dz3o, (const TA *)fw.V3, e, st));
         e = Epi{nullptr, w.dy2r, nullptr, w.y1r, nullptr, w.dz1o, nullptr};
-        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_BWD, mr, kFitPad, ks * kFitPad, (const TA *)w.dz2o, (const TA *)fw.V2, e, st));
+        DP_TIMED("fit_bwd2", st, launch_gemm<TA, TR>(EPI_BWD, mr, kFitPad, ks * kFitPad, (const TA *)w.dz2o, (const TA *)fw.V2, e, st));
         e = Epi{nullptr, nullptr, nullptr, nullptr, w.dDr, nullptr, nullptr};
-        DP_TIMED("fit_gemm", st, launch_gemm<TA, TR>(EPI_LIN, mr, kDdim, ks * kFitPad, (const TA *)w.dz1o, (const TA *)fw.V1, e, st));
-        DP_TIMED("dT", st, launch_dT<TR>(n, (const TR *)w.dDr, (const TR *)w.T, (TR *)w.dT, st));
-        if ((s = step_check("fitting_backward", st)) != DP_OK) return s;
+        DP_TIMED("fit_bwd1", st, launch_gemm<TA, TR>(EPI_LIN, mr, kDdim, ks * kFitPad, (const TA *)w.dz1o, (const TA *)fw.V1, e, st));
         if (PLAIN) {
+            DP_TIMED("dT", st, launch_dT<TR>(n, (const TR *)w.dDr, (const TR *)w.T, (TR *)w.dT, st));
+            if ((s = step_check("fitting_backward", st)) != DP_OK) return s;
             if ((s = plain_backward<TR>(m, a.nl, n, w.dT, a.force, w.w_atom, st)) != DP_OK) return s;
         } else {
-            launch_fill_zero(a.force, 3L * n, st);
-            DP_TIMED("emb_bwd", st, launch_emb_bwd(m, a.nl, n, a.x, a.precision, w.dT, a.force, w.w_atom, st));
+            if ((s = step_check("fitting_backward", st)) != DP_OK) return s;
+            // dE/dT is formed inside the fused backward from dE/dD and T
+            DP_TIMED("emb_bwd", st, launch_emb_bwd(m, a.nl, n, a.x, a.precision, w.T, w.dDr, w.rec, w.rcnt, a.force, w.w_atom, st));
+            DP_TIMED("force_gather", st, launch_force_gather(a.nl, n, a.precision, a.force, st));
             if ((s = step_check("emb_bwd", st)) != DP_OK) return s;
         }
     }
@@ -147,16 +155,16 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
 
 }  // namespace
 
-size_t ws_bytes_for_atoms(int natoms, int precision)
+size_t ws_bytes_for_atoms(int natoms, int precision, int sel)
 {
-    return ws_bytes_for((int)round_up(natoms, kRowPad), precision);
+    return ws_bytes_for((int)round_up(natoms, kRowPad), precision, sel);
 }
 
-dp_status ensure_ws(dp_nlist *nl, int precision)
+dp_status ensure_ws(dp_nlist *nl, int precision, int sel)
 {
     int np = (int)round_up(nl->alloc_atoms, kRowPad);
-    size_t need = ws_bytes_for(np, DP_FP64);
-    size_t need_bf = ws_bytes_for(np, DP_MIXED_BF16);
+    size_t need = ws_bytes_for(np, DP_FP64, sel);
+    size_t need_bf = ws_bytes_for(np, DP_MIXED_BF16, sel);
     if (need_bf > need) need = need_bf;   // the largest of the three layouts
     (void)precision;
     if (nl->ws_bytes >= need) return DP_OK;
@@ -174,7 +182,7 @@ dp_status ensure_ws(dp_nlist *nl, int precision)
 dp_status run_compressed(const ComputeArgs &a, hipStream_t st)
 {
     int np = (int)round_up(a.nl->alloc_atoms, kRowPad);
-    WS w = carve(a.nl->ws, np, a.precision);
+    WS w = carve(a.nl->ws, np, a.precision, a.m->cfg.sel);
     if (a.precision == DP_FP64) return run_t<double, double, false>(a, w, np, a.m->w64, a.m->fitb_d, st);
     if (a.precision == DP_FP32) return run_t<float, float, false>(a, w, np, a.m->w32, a.m->fitb_f, st);
     return run_t<__bf16, float, false>(a, w, np, a.m->wbf, a.m->fitb_f, st);
@@ -183,7 +191,7 @@ dp_status run_compressed(const ComputeArgs &a, hipStream_t st)
 dp_status run_plain(const ComputeArgs &a, hipStream_t st)
 {
     int np = (int)round_up(a.nl->alloc_atoms, kRowPad);
-    WS w = carve(a.nl->ws, np, a.precision);
+    WS w = carve(a.nl->ws, np, a.precision, a.m->cfg.sel);
     if (a.precision == DP_FP64) return run_t<double, double, true>(a, w, np, a.m->w64, a.m->fitb_d, st);
     if (a.precision == DP_FP32) return run_t<float, float, true>(a, w, np, a.m->w32, a.m->fitb_f, st);
     return run_t<__bf16, float, true>(a, w, np, a.m->wbf, a.m->fitb_f, st);

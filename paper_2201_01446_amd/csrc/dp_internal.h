@@ -87,6 +87,9 @@ struct dp_nlist {
     int *cnt = nullptr;      // [natoms]
     int *nei = nullptr;      // [natoms * cap]
     int *shift = nullptr;    // [natoms * cap], int8 x3 packed image shift
+    float *dist = nullptr;   // [natoms * cap], distance at build (the sort key)
+    short *rev = nullptr;    // [natoms * cap], slot of (i, -shift) in j's list, or -1
+    void *pg = nullptr;      // [natoms * cap * 3] reals: dE_i/dr_ij per candidate slot
     int *flags = nullptr;    // [kNumFlags]
     // per-configuration scratch of dp_compute
     void *ws = nullptr;
@@ -212,10 +215,13 @@ void launch_to_double(long n, const T *a, double *b, hipStream_t st);
 // GEMM operand matrix (n rows, ncols logical columns) to FP64 (hi + lo for BF16)
 template <typename T>
 void launch_op_to_double(int n, int ncols, const T *a, double *b, hipStream_t st);
+// rec/rcnt: the forward's compacted neighbor records (sel slots per atom) and
+// their counts, written by launch_emb_fwd and read by launch_emb_bwd
 void launch_emb_fwd(const dp_model *m, const dp_nlist *nl, int n, const double *x, int precision, void *T,
-                    void *D, int *nnei, hipStream_t st);
+                    void *D, void *rec, int *rcnt, int *nnei, int *nseg, hipStream_t st);
 void launch_emb_bwd(const dp_model *m, const dp_nlist *nl, int n, const double *x, int precision,
-                    const void *dT, double *force, double *w_atom, hipStream_t st);
+                    const void *T, const void *dD, const void *rec, const int *rcnt, double *force,
+                    double *w_atom, hipStream_t st);
 
 struct ComputeArgs {
     const dp_model *m;
@@ -225,6 +231,7 @@ struct ComputeArgs {
     int precision;
     double *energy, *force, *virial, *atom_energy;   // force: never NULL when need_forces
     int *nnei_out;
+    int *nseg_out = nullptr;
     double *T_out, *D_out;
     bool need_forces;
     int phase;   // 0: whole step; 1: forward only, activations kept; 2: backward from kept activations
@@ -237,8 +244,14 @@ dp_status plain_forward(const dp_model *m, dp_nlist *nl, int n, const double *x,
 template <typename real>
 dp_status plain_backward(const dp_model *m, dp_nlist *nl, int n, const void *dT, double *force, double *w_atom,
                          hipStream_t st);
-dp_status ensure_ws(dp_nlist *nl, int precision);
-size_t ws_bytes_for_atoms(int natoms, int precision);
+dp_status ensure_ws(dp_nlist *nl, int precision, int sel);
+// Reverse slots of the candidate lists of atoms [off, off + n) (after a build).
+void launch_reverse(dp_nlist *nl, int off, int n, hipStream_t st);
+// F_i = (F_i as written by the backward: sum_j dE_i/dr_ij) - sum over the
+// candidates j of i of dE_j/dr_ji, read from the pair gradients at the
+// reverse slot; deterministic (fixed order), no atomics.
+void launch_force_gather(const dp_nlist *nl, int n, int precision, double *force, hipStream_t st);
+size_t ws_bytes_for_atoms(int natoms, int precision, int sel);
 dp_status run_compressed(const ComputeArgs &a, hipStream_t st);
 dp_status run_plain(const ComputeArgs &a, hipStream_t st);
 void launch_verlet_kick_drift(double *x, double *v, const double *f, int n, double kick, double dt,

@@ -7,30 +7,39 @@
 //     s = w(r)/r, R_j = s (1, x/r, y/r, z/r)                      (Eq. 1)
 //     G_j = f_theta(s): the M quintics of s's table interval      (Sec. 3.2)
 //   T = desc_scale * sum_j R_j^T G_j   (4 x M), D = T<^T T (M< x M)  (Eq. 2)
-// G is never stored: each lane evaluates its columns of G_j in registers and
-// folds them into T at once (the kernel fusion of Sec. 3.3/3.4.1).  Padded
-// neighbors do not exist here: the loop runs over the n_i real neighbors only
-// (the redundancy removal of Sec. 3.4.2; with unnormalised R the padded rows
-// would contribute exact zeros).
+// G is never stored (the kernel fusion of Sec. 3.3/3.4.1) and only the n_i
+// real neighbors are visited (the redundancy removal of Sec. 3.4.2; with
+// unnormalised R the padded rows would contribute exact zeros).
 //
-// Work distribution (one 64-lane wavefront per atom):
-//   lanes are split into NG groups of GL = 128/CPL lanes; lane l of a group
-//   owns the CPL columns eta = l + GL*c.  Group g walks the g-th contiguous
-//   chunk of the distance-sorted neighbor list, so consecutive neighbors
-//   mostly share a table interval and the lane keeps that interval's
-//   coefficients in registers, reloading only when the interval changes.
-//   Neighbor data is staged once in LDS and read as group-uniform
-//   broadcasts.  The forward needs no cross-lane traffic inside the loop;
-//   partial T's of the groups are summed once at the end.
+// Interval-moment form of the contraction.  In table interval theta the
+// embedding is G_eta(s) = sum_e a[theta][eta][e] t^e with t = s - x_theta, so
+// for the neighbors j whose s falls in theta
+//   sum_j R_jk G_j,eta = sum_e a[theta][eta][e] M[theta][k][e],
+//   M[theta][k][e] = sum_{j in theta} R_jk t_j^e      (4 x 6 moments).
+// The neighbor list is sorted by distance and s decreases with r, so the
+// neighbors of one interval form consecutive runs ("segments"; about 20 per
+// atom in copper against about 178 neighbors).  The forward therefore forms
+// 24 moments per neighbor and then 24 FMA per (segment, column), instead of
+// 9 FMA per (neighbor, column).  The backward does the same on the other
+// side: with dT = dE/dT (desc_scale applied),
+//   dE/dR_jk  = sum_eta dT_k,eta G_j,eta = sum_e B[theta][k][e] t_j^e,
+//   B[theta][k][e] = sum_eta dT_k,eta a[theta][eta][e],
+//   dE/ds_j  += sum_k R_jk d/dt (sum_e B[theta][k][e] t^e) at t_j,
+// so each segment costs 24 FMA per column once, and each neighbor two
+// quintics per k.  Then g_ij = dE_i/dr_ij by the chain rule through Eq. 1:
+// F_i = sum_j g_ij is written directly and W_i -= r_ij (x) g_ij; each g_ij is
+// stored at its candidate slot, and a gather after the kernel subtracts from
+// F_j the g_ij of every atom i that lists j (no atomics, a fixed order).
+// Neighbors clamped to the table end form their own segment and get G' = 0.
+// A run split because atoms moved since the list was sorted is simply two
+// segments of the same interval.
 //
-// Backward (the adjoint of the same fused step, G recomputed from the
-// table): with dT = dE/dT (4 x M) per atom,
-//   dE/dR_jk  = desc_scale * sum_eta dT_k,eta G_j,eta
-//   dE/ds_j  += desc_scale * sum_eta (sum_k dT_k,eta R_jk) G'_j,eta
-//   g_ij = dE_i/dr_ij by the chain rule through Eq. 1,
-//   F_i += g_ij, F_j -= g_ij (FP64 atomics), W_i -= r_ij (x) g_ij.
-// The sums over eta are reduced across the lanes of a group with DPP row
-// operations (quad_perm, row_half_mirror, row_mirror).
+// Work distribution (one 64-lane wavefront per atom, neighbor data in LDS):
+//   moments and B: quad q of the wave owns one segment per round, its four
+//   lanes split the segment's neighbors (moments) or the 128 columns (B),
+//   and the quad's partial sums meet in two DPP steps;
+//   contraction into T: each lane owns columns eta = lane and lane + 64;
+//   per-neighbor tail of the backward: each lane owns neighbors.
 
 #include "dp_internal.h"
 #include "emb_common.h"
@@ -42,62 +51,33 @@ namespace dp {
 
 namespace {
 
-// Coefficients of CPL columns of interval th into registers.
-template <typename real, int CPL, int GL>
-__device__ inline void load_coef(const real *tab, int th, int l, real (&a)[CPL][6]);
+constexpr int kSegRound = 16;   // segments per round: one per quad of the wave
 
-template <>
-__device__ inline void load_coef<float, 8, 16>(const float *tab, int th, int l, float (&a)[8][6])
+__device__ inline void wave_sync()
 {
-#pragma unroll
-    for (int c = 0; c < 8; c++) {
-        const float4 *p = reinterpret_cast<const float4 *>(tab + ((long)th * kM + l + 16 * c) * 8);
-        float4 u = p[0], v = p[1];
-        a[c][0] = u.x; a[c][1] = u.y; a[c][2] = u.z; a[c][3] = u.w; a[c][4] = v.x; a[c][5] = v.y;
-    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <>
-__device__ inline void load_coef<float, 4, 32>(const float *tab, int th, int l, float (&a)[4][6])
+// The 6 coefficients of column c of interval th.
+__device__ inline void coef_col(const float *tab, int th, int c, float (&a)[6])
 {
-#pragma unroll
-    for (int c = 0; c < 4; c++) {
-        const float4 *p = reinterpret_cast<const float4 *>(tab + ((long)th * kM + l + 32 * c) * 8);
-        float4 u = p[0], v = p[1];
-        a[c][0] = u.x; a[c][1] = u.y; a[c][2] = u.z; a[c][3] = u.w; a[c][4] = v.x; a[c][5] = v.y;
-    }
+    const float *p = tab + ((long)th * kM + c) * 8;   // FP32 rows: 6 values + 2 pads
+    float4 u = *reinterpret_cast<const float4 *>(p);
+    float2 v = *reinterpret_cast<const float2 *>(p + 4);
+    a[0] = u.x; a[1] = u.y; a[2] = u.z; a[3] = u.w; a[4] = v.x; a[5] = v.y;
+}
+__device__ inline void coef_col(const double *tab, int th, int c, double (&a)[6])
+{
+    const double2 *p = reinterpret_cast<const double2 *>(tab + ((long)th * kM + c) * 6);
+    double2 u = p[0], v = p[1], w = p[2];
+    a[0] = u.x; a[1] = u.y; a[2] = v.x; a[3] = v.y; a[4] = w.x; a[5] = w.y;
 }
 
-template <>
-__device__ inline void load_coef<double, 4, 32>(const double *tab, int th, int l, double (&a)[4][6])
-{
-#pragma unroll
-    for (int c = 0; c < 4; c++) {
-        const double2 *p = reinterpret_cast<const double2 *>(tab + ((long)th * kM + l + 32 * c) * 6);
-        double2 u = p[0], v = p[1], w = p[2];
-        a[c][0] = u.x; a[c][1] = u.y; a[c][2] = v.x; a[c][3] = v.y; a[c][4] = w.x; a[c][5] = w.y;
-    }
-}
-
-template <>
-__device__ inline void load_coef<double, 2, 64>(const double *tab, int th, int l, double (&a)[2][6])
-{
-#pragma unroll
-    for (int c = 0; c < 2; c++) {
-        const double2 *p = reinterpret_cast<const double2 *>(tab + ((long)th * kM + l + 64 * c) * 6);
-        double2 u = p[0], v = p[1], w = p[2];
-        a[c][0] = u.x; a[c][1] = u.y; a[c][2] = v.x; a[c][3] = v.y; a[c][4] = w.x; a[c][5] = w.y;
-    }
-}
-
+// f = sum_e a[e] t^e and its derivative.
 template <typename real>
-__device__ inline real horner(const real (&a)[6], real t)
-{
-    return fma(fma(fma(fma(fma(a[5], t, a[4]), t, a[3]), t, a[2]), t, a[1]), t, a[0]);
-}
-
-template <typename real>
-__device__ inline void horner2(const real (&a)[6], real t, real &f, real &fp)
+__device__ inline void horner2(const real *a, real t, real &f, real &fp)
 {
     real p = a[5], q = a[5];
     p = fma(p, t, a[4]);
@@ -110,6 +90,19 @@ __device__ inline void horner2(const real (&a)[6], real t, real &f, real &fp)
     q = fma(q, t, p);
     f = fma(p, t, a[0]);
     fp = q;
+}
+
+__device__ inline float quad_sum(float v)
+{
+    v += dpp_f<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f<0x4E>(v);   // quad_perm [2,3,0,1]
+    return v;
+}
+__device__ inline double quad_sum(double v)
+{
+    v += dpp_d<0xB1>(v);
+    v += dpp_d<0x4E>(v);
+    return v;
 }
 
 // Sum over the GL lanes of a group, result in every lane of the group.
@@ -137,171 +130,328 @@ __device__ inline double group_sum(double v)
     return v;
 }
 
-template <typename T> __device__ inline T cvt(float v);
-template <> __device__ inline float cvt<float>(float v) { return v; }
-template <> __device__ inline double cvt<double>(float v) { return v; }
-template <> __device__ inline __hip_bfloat16 cvt<__hip_bfloat16>(float v) { return __float2bfloat16(v); }
-template <typename T> __device__ inline T cvtd(double v);
-template <> __device__ inline double cvtd<double>(double v) { return v; }
-template <> __device__ inline float cvtd<float>(double v) { return (float)v; }
-template <> __device__ inline __hip_bfloat16 cvtd<__hip_bfloat16>(double v) { return __float2bfloat16((float)v); }
+// Starts of the runs of equal interval in the neighbor list: seg[0..nseg-1],
+// seg[nseg] = nn.  Returns nseg (uniform over the wave).
+template <typename real>
+__device__ int find_segments(const NbrLDS<real> &L, int nn, int lane, int *seg)
+{
+    int nseg = 0;
+    for (int base = 0; base < nn; base += 64) {
+        int k = base + lane;
+        bool head = k < nn && (k == 0 || L.th[k] != L.th[k - 1]);
+        unsigned long long m = __ballot(head);
+        if (head) seg[nseg + __popcll(m & ((1ull << lane) - 1ull))] = k;
+        nseg += __popcll(m);
+    }
+    if (lane == 0) seg[nseg] = nn;
+    wave_sync();
+    return nseg;
+}
+
+constexpr int seg_bytes(int sel) { return ((sel + 1) * 4 + 15) / 16 * 16; }
+
+// Per-wave LDS of the forward: neighbor arrays, T (4 x M), the moments of one
+// round of segments, segment starts.
+template <typename real>
+constexpr int fwd_lds_bytes(int sel)
+{
+    constexpr int al = (int)sizeof(V4<real>);   // keeps every wave's slice aligned
+    return (nbr_lds_bytes<real>(sel, ENV_FWD) + 4 * kM * (int)sizeof(real) + kSegRound * 24 * (int)sizeof(real) +
+            seg_bytes(sel) + al - 1) / al * al;
+}
+
+// Per-wave LDS of the backward: neighbor arrays, dT as (dT_0c, .., dT_3c)
+// per column c, B of one round of segments, segment starts.
+template <typename real>
+constexpr int bwd_lds_bytes(int sel)
+{
+    constexpr int al = (int)sizeof(V4<real>);
+    return (nbr_lds_bytes<real>(sel, ENV_BWD) + kM * (int)sizeof(V4<real>) + kSegRound * 24 * (int)sizeof(real) +
+            seg_bytes(sel) + al - 1) / al * al;
+}
 
 // -------------------------------------------------------------- forward
-template <typename real, typename TD, int CPL>
+template <typename real, typename TD>
 __global__ void __launch_bounds__(256) k_emb_fwd(int natoms, EnvArgs A, const real *__restrict__ tab,
                                                  real sigma, real *__restrict__ T_out,
-                                                 TD *__restrict__ D_out, int *__restrict__ nnei_out)
+                                                 TD *__restrict__ D_out, int *__restrict__ nnei_out,
+                                                 int *__restrict__ nseg_out)
+{
+    HIP_DYNAMIC_SHARED(uint4, smem_raw)   // 16-byte aligned
+    char *base = reinterpret_cast<char *>(smem_raw);
+    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int i = blockIdx.x * (blockDim.x >> 6) + wave;
+    base += wave * fwd_lds_bytes<real>(A.sel);
+    NbrLDS<real> L = carve<real>(base, A.sel, ENV_FWD);
+    char *p = base + nbr_lds_bytes<real>(A.sel, ENV_FWD);
+    real *Tl = reinterpret_cast<real *>(p);   // 4 x M
+    p += 4 * kM * sizeof(real);
+    real *Ms = reinterpret_cast<real *>(p);   // kSegRound x 24
+    p += kSegRound * 24 * sizeof(real);
+    int *seg = reinterpret_cast<int *>(p);
+    bool live = i < natoms;
+    int nn = 0, n_in = 0, oob = 0;
+    if (live) nn = build_env<real, ENV_FWD>(i, A, L, lane, n_in, oob);
+    __syncthreads();
+    if (!live) return;
+    int nseg = find_segments(L, nn, lane, seg);
+
+    int q = lane >> 2, ql = lane & 3;
+    real T0[4] = {0, 0, 0, 0}, T1[4] = {0, 0, 0, 0};   // columns lane, lane + 64
+    for (int s0 = 0; s0 < nseg; s0 += kSegRound) {
+        int ns = min(kSegRound, nseg - s0);
+        // moments of segment s0 + q: the quad's lanes take every 4th neighbor
+        real M[4][6];
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+#pragma unroll
+            for (int e = 0; e < 6; e++) M[k][e] = 0;
+        if (q < ns) {
+            int e1 = seg[s0 + q + 1];
+            for (int k = seg[s0 + q] + ql; k < e1; k += 4) {
+                real t = L.t[k];
+                V4<real> R = L.R[k];
+                real pw = 1;
+#pragma unroll
+                for (int e = 0; e < 6; e++) {
+                    M[0][e] = fma(R.x, pw, M[0][e]);
+                    M[1][e] = fma(R.y, pw, M[1][e]);
+                    M[2][e] = fma(R.z, pw, M[2][e]);
+                    M[3][e] = fma(R.w, pw, M[3][e]);
+                    pw *= t;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+#pragma unroll
+            for (int e = 0; e < 6; e++) M[k][e] = quad_sum(M[k][e]);
+        if (q < ns && ql == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+#pragma unroll
+                for (int e = 0; e < 6; e++) Ms[q * 24 + k * 6 + e] = M[k][e];
+        }
+        wave_sync();
+        // T[k][c] += sum_e a[theta][c][e] M[k][e], lanes over columns; the
+        // coefficients of up to four segments are requested before any is used
+        for (int s1 = 0; s1 < ns; s1 += 4) {
+            real a0[4][6], a1[4][6];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                if (s1 + u < ns) {
+                    int th = L.th[seg[s0 + s1 + u]] & ~kOobBit;
+                    coef_col(tab, th, lane, a0[u]);
+                    coef_col(tab, th, lane + 64, a1[u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                if (s1 + u < ns) {
+                    const real *m = Ms + (s1 + u) * 24;
+#pragma unroll
+                    for (int k = 0; k < 4; k++)
+#pragma unroll
+                        for (int e = 0; e < 6; e++) {
+                            real mv = m[k * 6 + e];
+                            T0[k] = fma(mv, a0[u][e], T0[k]);
+                            T1[k] = fma(mv, a1[u][e], T1[k]);
+                        }
+                }
+            }
+        }
+        wave_sync();   // Ms is rewritten by the next round
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        T0[k] *= sigma;
+        T1[k] *= sigma;
+        Tl[k * kM + lane] = T0[k];
+        Tl[k * kM + lane + 64] = T1[k];
+        T_out[(long)i * 4 * kM + k * kM + lane] = T0[k];
+        T_out[(long)i * 4 * kM + k * kM + lane + 64] = T1[k];
+    }
+    wave_sync();
+    // D[a][b] = sum_k T[k][a] T[k][b], a < M<: lane owns b = lane, lane + 64
+#pragma unroll 4
+    for (int a = 0; a < kMlt; a++) {
+        real d0 = 0, d1 = 0;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            real ta = Tl[k * kM + a];
+            d0 = fma(ta, T0[k], d0);
+            d1 = fma(ta, T1[k], d1);
+        }
+        store_op(D_out, i, a * kM + lane, kDdim, (double)d0);
+        store_op(D_out, i, a * kM + lane + 64, kDdim, (double)d1);
+    }
+    // counters last: nothing in this kernel waits for these atomics
+    if (nnei_out && lane == 0) nnei_out[i] = nn;
+    if (nseg_out && lane == 0) nseg_out[i] = nseg;
+    record_flags<real>(A, lane, n_in, oob);
+}
+
+// ------------------------------------------------------------- backward
+// CPL: columns per lane in the dE/dT prologue (lanes in NG groups of GL).
+template <typename real, int CPL>
+__global__ void __launch_bounds__(256) k_emb_bwd(int natoms, EnvArgs A, const real *__restrict__ tab,
+                                                 real sigma, const real *__restrict__ T,
+                                                 const real *__restrict__ dD, double *__restrict__ force,
+                                                 double *__restrict__ w_atom)
 {
     constexpr int GL = kM / CPL, NG = 64 / GL;
     HIP_DYNAMIC_SHARED(uint4, smem_raw)   // 16-byte aligned
-    char *smem = reinterpret_cast<char *>(smem_raw);
+    char *base = reinterpret_cast<char *>(smem_raw);
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int i = blockIdx.x * (blockDim.x >> 6) + wave;
-    real *Tl;
-    NbrLDS<real> L = carve<real>(smem + wave * lds_bytes_per_wave<real>(A.sel, false), A.sel, false, Tl);
+    base += wave * bwd_lds_bytes<real>(A.sel);
+    NbrLDS<real> L = carve<real>(base, A.sel, ENV_BWD);
+    char *p = base + nbr_lds_bytes<real>(A.sel, ENV_BWD);
+    V4<real> *dTl = reinterpret_cast<V4<real> *>(p);   // per column
+    p += kM * sizeof(V4<real>);
+    real *Bs = reinterpret_cast<real *>(p);             // kSegRound x 24
+    p += kSegRound * 24 * sizeof(real);
+    int *seg = reinterpret_cast<int *>(p);
     bool live = i < natoms;
-    int nn = 0, n_in = 0, oob = 0;
-    if (live) nn = build_env<real, false>(i, A, L, lane, n_in, oob);
+    int nn = 0;
+    if (live) nn = load_env<real>(i, A, L, lane);
     __syncthreads();
     if (!live) return;
-    record_flags<real>(A, lane, n_in, oob);
-    if (nnei_out && lane == 0) nnei_out[i] = nn;
 
-    int g = lane / GL, l = lane % GL;
-    int chunk = (nn + NG - 1) / NG;
-    int beg = g * chunk, end = min(nn, beg + chunk);
-    real acc[4][CPL];
-#pragma unroll
-    for (int c = 0; c < CPL; c++) acc[0][c] = acc[1][c] = acc[2][c] = acc[3][c] = 0;
-    real a[CPL][6];
-    int cur = -1;
-    for (int k = beg; k < end; k++) {
-        int th = L.I[k].x & ~kOobBit;
-        real t = L.P[k].x;
-        V4<real> R = L.R[k];
-        if (th != cur) {
-            load_coef<real, CPL, GL>(tab, th, l, a);
-            cur = th;
-        }
-#pragma unroll
-        for (int c = 0; c < CPL; c++) {
-            real f = horner<real>(a[c], t);
-            acc[0][c] = fma(R.x, f, acc[0][c]);
-            acc[1][c] = fma(R.y, f, acc[1][c]);
-            acc[2][c] = fma(R.z, f, acc[2][c]);
-            acc[3][c] = fma(R.w, f, acc[3][c]);
-        }
-    }
-    // sum the groups' partial T
-#pragma unroll
-    for (int off = GL; off < 64; off <<= 1)
-#pragma unroll
-        for (int c = 0; c < CPL; c++)
-#pragma unroll
-            for (int k = 0; k < 4; k++) acc[k][c] += __shfl_xor(acc[k][c], off);
-    if (g == 0) {
+    // dE/dT from dE/dD through D = T<^T T (Eq. 2; T already carries desc_scale):
+    //   dT[k][b] = sum_{a<M<} dD[a][b] T[k][a] + [b<M<] sum_c dD[b][c] T[k][c].
+    // Group g takes the rows a of dD in [g APG, (g+1) APG), each lane its CPL
+    // columns b = l + GL c; the second term's sum over c is a group
+    // reduction, added at the lane that owns column b = a; the groups'
+    // partials are then summed and group 0 parks dT in LDS.
+    {
+        constexpr int APG = kMlt / NG;
+        int g = lane / GL, l = lane % GL;
+        const real *Ti = T + (long)i * 4 * kM;
+        const real *dDi = dD + (long)i * kDdim;
+        real dt[4][CPL], tc[4][CPL];
 #pragma unroll
         for (int c = 0; c < CPL; c++)
 #pragma unroll
             for (int k = 0; k < 4; k++) {
-                real v = sigma * acc[k][c];
-                Tl[k * kM + l + GL * c] = v;
-                T_out[(long)i * 4 * kM + k * kM + l + GL * c] = v;
+                tc[k][c] = Ti[k * kM + l + GL * c];
+                dt[k][c] = 0;
             }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // D[a][b] = sum_k T[k][a] T[k][b], a < M<
-    for (int o = lane; o < kDdim; o += 64) {
-        int aa = o >> 7, bb = o & (kM - 1);
-        real v = Tl[aa] * Tl[bb];
-        v = fma(Tl[kM + aa], Tl[kM + bb], v);
-        v = fma(Tl[2 * kM + aa], Tl[2 * kM + bb], v);
-        v = fma(Tl[3 * kM + aa], Tl[3 * kM + bb], v);
-        store_op(D_out, i, o, kDdim, (double)v);
-    }
-}
-
-// ------------------------------------------------------------- backward
-template <typename real, int CPL>
-__global__ void __launch_bounds__(256) k_emb_bwd(int natoms, EnvArgs A, const real *__restrict__ tab,
-                                                 real sigma, const real *__restrict__ dT,
-                                                 double *__restrict__ force, double *__restrict__ w_atom)
-{
-    constexpr int GL = kM / CPL, NG = 64 / GL;
-    HIP_DYNAMIC_SHARED(uint4, smem_raw)   // 16-byte aligned
-    char *smem = reinterpret_cast<char *>(smem_raw);
-    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int i = blockIdx.x * (blockDim.x >> 6) + wave;
-    real *Tl;
-    NbrLDS<real> L = carve<real>(smem + wave * lds_bytes_per_wave<real>(A.sel, true), A.sel, true, Tl);
-    bool live = i < natoms;
-    int nn = 0, n_in = 0, oob = 0;
-    if (live) nn = build_env<real, true>(i, A, L, lane, n_in, oob);
-    __syncthreads();
-    if (!live) return;
-
-    int g = lane / GL, l = lane % GL;
-    real dt[4][CPL];
 #pragma unroll
-    for (int c = 0; c < CPL; c++)
+        for (int qa = 0; qa < APG; qa++) {
+            int a0 = g * APG + qa;
+            real ta[4], s2[4];
 #pragma unroll
-        for (int k = 0; k < 4; k++) dt[k][c] = sigma * dT[(long)i * 4 * kM + k * kM + l + GL * c];
-    int chunk = (nn + NG - 1) / NG;
-    int beg = g * chunk, end = min(nn, beg + chunk);
-    real a[CPL][6];
-    int cur = -1;
+            for (int k = 0; k < 4; k++) {
+                ta[k] = Ti[k * kM + a0];
+                s2[k] = 0;
+            }
+#pragma unroll
+            for (int c = 0; c < CPL; c++) {
+                real v = dDi[a0 * kM + l + GL * c];
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    dt[k][c] = fma(v, ta[k], dt[k][c]);
+                    s2[k] = fma(v, tc[k][c], s2[k]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                s2[k] = group_sum<GL>(s2[k]);
+                dt[k][0] += l == a0 ? s2[k] : (real)0;
+            }
+        }
+#pragma unroll
+        for (int off = GL; off < 64; off <<= 1)
+#pragma unroll
+            for (int c = 0; c < CPL; c++)
+#pragma unroll
+                for (int k = 0; k < 4; k++) dt[k][c] += __shfl_xor(dt[k][c], off);
+        if (g == 0) {
+#pragma unroll
+            for (int c = 0; c < CPL; c++)
+                dTl[l + GL * c] = V4<real>{sigma * dt[0][c], sigma * dt[1][c], sigma * dt[2][c], sigma * dt[3][c]};
+        }
+    }
+    int nseg = find_segments(L, nn, lane, seg);   // its wave barrier also publishes dT
+
+    int q = lane >> 2, ql = lane & 3;
     real Fi0 = 0, Fi1 = 0, Fi2 = 0;
     real W[9];
 #pragma unroll
-    for (int q = 0; q < 9; q++) W[q] = 0;
-    for (int k = beg; k < end; k++) {
-        int2 I = L.I[k];
-        V4<real> P = L.P[k];
-        V4<real> R = L.R[k];
-        int th = I.x & ~kOobBit;
-        if (th != cur) {
-            load_coef<real, CPL, GL>(tab, th, l, a);
-            cur = th;
-        }
-        real dR0 = 0, dR1 = 0, dR2 = 0, dR3 = 0, dsG = 0;
+    for (int r = 0; r < 9; r++) W[r] = 0;
+    for (int s0 = 0; s0 < nseg; s0 += kSegRound) {
+        int ns = min(kSegRound, nseg - s0);
+        // B[k][e] = sum_c dT[k][c] a[theta][c][e] of segment s0 + q; the
+        // quad's lanes take columns c = 4 m + ql
+        real B[4][6];
 #pragma unroll
-        for (int c = 0; c < CPL; c++) {
-            real f, fp;
-            horner2<real>(a[c], P.x, f, fp);
-            dR0 = fma(dt[0][c], f, dR0);
-            dR1 = fma(dt[1][c], f, dR1);
-            dR2 = fma(dt[2][c], f, dR2);
-            dR3 = fma(dt[3][c], f, dR3);
-            real av = dt[0][c] * R.x;
-            av = fma(dt[1][c], R.y, av);
-            av = fma(dt[2][c], R.z, av);
-            av = fma(dt[3][c], R.w, av);
-            dsG = fma(av, fp, dsG);
+        for (int k = 0; k < 4; k++)
+#pragma unroll
+            for (int e = 0; e < 6; e++) B[k][e] = 0;
+        if (q < ns) {
+            int th = L.th[seg[s0 + q]] & ~kOobBit;
+#pragma unroll 4
+            for (int m = 0; m < kM / 4; m++) {
+                int c = 4 * m + ql;
+                V4<real> d = dTl[c];
+                real a[6];
+                coef_col(tab, th, c, a);
+#pragma unroll
+                for (int e = 0; e < 6; e++) {
+                    B[0][e] = fma(d.x, a[e], B[0][e]);
+                    B[1][e] = fma(d.y, a[e], B[1][e]);
+                    B[2][e] = fma(d.z, a[e], B[2][e]);
+                    B[3][e] = fma(d.w, a[e], B[3][e]);
+                }
+            }
         }
-        dR0 = group_sum<GL>(dR0);
-        dR1 = group_sum<GL>(dR1);
-        dR2 = group_sum<GL>(dR2);
-        dR3 = group_sum<GL>(dR3);
-        dsG = group_sum<GL>(dsG);
-        if (I.x & kOobBit) dsG = 0;
-        if (l == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+#pragma unroll
+            for (int e = 0; e < 6; e++) B[k][e] = quad_sum(B[k][e]);
+        if (q < ns && ql == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+#pragma unroll
+                for (int e = 0; e < 6; e++) Bs[q * 24 + k * 6 + e] = B[k][e];
+        }
+        wave_sync();
+        // the neighbors of these segments, one per lane: dE/dR_j and dE/ds_j
+        // from B, then the chain rule through Eq. 1 and the scatter
+        int kb = seg[s0], ke = seg[s0 + ns];
+        int cur = -1;   // segment (relative to s0) of the last neighbor before this chunk
+        for (int b0 = kb; b0 < ke; b0 += 64) {
+            int k = b0 + lane;
+            bool in = k < ke;
+            bool head = in && (k == kb || L.th[k] != L.th[k - 1]);
+            unsigned long long hm = __ballot(head);
+            int sidx = cur + __popcll(hm & ((2ull << lane) - 1ull));   // heads up to and including k
+            cur += __popcll(hm);
+            if (!in) continue;
+            int th = L.th[k];
+            real t = L.t[k];
             V4<real> d = L.Dv[k];
-            real rinv = P.z, s = P.w, sp = P.y;
+            int slot = L.j[k];
+            const real *b = Bs + sidx * 24;
+            real dR[4], Q[4];
+#pragma unroll
+            for (int kk = 0; kk < 4; kk++) horner2<real>(b + kk * 6, t, dR[kk], Q[kk]);
+            real rinv, s, sp;
+            env_geom<real>(A, d, rinv, s, sp);
             real h0 = d.x * rinv, h1 = d.y * rinv, h2 = d.z * rinv;
+            // dE/ds through G: sum_k R_k dB_k/dt with R = s (1, h); no G' past the table end
+            real dsG = (th & kOobBit) ? (real)0 : s * (Q[0] + Q[1] * h0 + Q[2] * h1 + Q[3] * h2);
             // R = s (1, h): dE/ds collects dR0 + dR.h; dE/dh = s dR[1..3]
-            real dEds = dsG + dR0 + dR1 * h0 + dR2 * h1 + dR3 * h2;
-            real u0 = s * dR1, u1 = s * dR2, u2 = s * dR3;
+            real dEds = dsG + dR[0] + dR[1] * h0 + dR[2] * h1 + dR[3] * h2;
+            real u0 = s * dR[1], u1 = s * dR[2], u2 = s * dR[3];
             real udh = u0 * h0 + u1 * h1 + u2 * h2;
             real c0 = dEds * sp;
             real g0 = c0 * h0 + (u0 - udh * h0) * rinv;
             real g1 = c0 * h1 + (u1 - udh * h1) * rinv;
             real g2 = c0 * h2 + (u2 - udh * h2) * rinv;
-            int j = I.y;
-            unsafeAtomicAdd(&force[3 * j], -(double)g0);
-            unsafeAtomicAdd(&force[3 * j + 1], -(double)g1);
-            unsafeAtomicAdd(&force[3 * j + 2], -(double)g2);
+            // dE_i/dr_ij, gathered into F_j after the kernel (no atomics)
+            put_pg<real>(A.pg, A.cap, i, slot, g0, g1, g2);
             Fi0 += g0;
             Fi1 += g1;
             Fi2 += g2;
@@ -309,24 +459,24 @@ __global__ void __launch_bounds__(256) k_emb_bwd(int natoms, EnvArgs A, const re
             W[3] -= d.y * g0; W[4] -= d.y * g1; W[5] -= d.y * g2;
             W[6] -= d.z * g0; W[7] -= d.z * g1; W[8] -= d.z * g2;
         }
+        wave_sync();   // Bs is rewritten by the next round
     }
-    // group leaders hold partials, other lanes zeros: sum over the wave
     for (int off = 32; off > 0; off >>= 1) {
         Fi0 += __shfl_xor(Fi0, off);
         Fi1 += __shfl_xor(Fi1, off);
         Fi2 += __shfl_xor(Fi2, off);
 #pragma unroll
-        for (int q = 0; q < 9; q++) W[q] += __shfl_xor(W[q], off);
+        for (int r = 0; r < 9; r++) W[r] += __shfl_xor(W[r], off);
     }
-    if (lane == 0) {
-        unsafeAtomicAdd(&force[3 * i], (double)Fi0);
-        unsafeAtomicAdd(&force[3 * i + 1], (double)Fi1);
-        unsafeAtomicAdd(&force[3 * i + 2], (double)Fi2);
+    if (lane == 0) {   // the gather then subtracts the neighbors' dE_j/dr_ji
+        force[3 * i] = (double)Fi0;
+        force[3 * i + 1] = (double)Fi1;
+        force[3 * i + 2] = (double)Fi2;
     }
     if (lane < 9) {
         real v = W[0];
 #pragma unroll
-        for (int q = 1; q < 9; q++) v = lane == q ? W[q] : v;
+        for (int r = 1; r < 9; r++) v = lane == r ? W[r] : v;
         w_atom[(long)i * 9 + lane] = (double)v;
     }
 }
@@ -334,43 +484,51 @@ __global__ void __launch_bounds__(256) k_emb_bwd(int natoms, EnvArgs A, const re
 }  // namespace
 
 // ---------------------------------------------------------- launchers
-template <typename real, typename TD, int CPL>
+template <typename real, typename TD>
 static void launch_fwd_t(const dp_model *m, const dp_nlist *nl, int n, const double *x, void *T,
-                         void *D, int *nnei, hipStream_t st)
+                         void *D, void *rec, int *rcnt, int *nnei, int *nseg, hipStream_t st)
 {
     EnvArgs A = make_env_args(m, nl, x);
+    A.rec = rec;
+    A.rcnt = rcnt;
+    A.pg = nl->pg;
     const real *tab = std::is_same<real, double>::value ? (const real *)m->tab64 : (const real *)m->tab32;
     int wpb = 4;
-    size_t lds = (size_t)wpb * lds_bytes_per_wave<real>(A.sel, false);
-    hipLaunchKernelGGL((k_emb_fwd<real, TD, CPL>), dim3(div_up(n, wpb)), dim3(64 * wpb), lds, st, n, A,
-                       tab, (real)m->cfg.desc_scale, (real *)T, (TD *)D, nnei);
+    size_t lds = (size_t)wpb * fwd_lds_bytes<real>(A.sel);
+    hipLaunchKernelGGL((k_emb_fwd<real, TD>), dim3(div_up(n, wpb)), dim3(64 * wpb), lds, st, n, A, tab,
+                       (real)m->cfg.desc_scale, (real *)T, (TD *)D, nnei, nseg);
 }
 
 template <typename real, int CPL>
-static void launch_bwd_t(const dp_model *m, const dp_nlist *nl, int n, const double *x,
-                         const void *dT, double *force, double *w_atom, hipStream_t st)
+static void launch_bwd_t(const dp_model *m, const dp_nlist *nl, int n, const double *x, const void *T,
+                         const void *dD, const void *rec, const int *rcnt, double *force, double *w_atom,
+                         hipStream_t st)
 {
     EnvArgs A = make_env_args(m, nl, x);
+    A.rec = const_cast<void *>(rec);
+    A.rcnt = const_cast<int *>(rcnt);
+    A.pg = nl->pg;
     const real *tab = std::is_same<real, double>::value ? (const real *)m->tab64 : (const real *)m->tab32;
     int wpb = 4;
-    size_t lds = (size_t)wpb * lds_bytes_per_wave<real>(A.sel, true);
+    size_t lds = (size_t)wpb * bwd_lds_bytes<real>(A.sel);
     hipLaunchKernelGGL((k_emb_bwd<real, CPL>), dim3(div_up(n, wpb)), dim3(64 * wpb), lds, st, n, A, tab,
-                       (real)m->cfg.desc_scale, (const real *)dT, force, w_atom);
+                       (real)m->cfg.desc_scale, (const real *)T, (const real *)dD, force, w_atom);
 }
 
 void launch_emb_fwd(const dp_model *m, const dp_nlist *nl, int n, const double *x, int precision,
-                    void *T, void *D, int *nnei, hipStream_t st)
+                    void *T, void *D, void *rec, int *rcnt, int *nnei, int *nseg, hipStream_t st)
 {
-    if (precision == DP_FP64) launch_fwd_t<double, double, 4>(m, nl, n, x, T, D, nnei, st);
-    else if (precision == DP_FP32) launch_fwd_t<float, float, 8>(m, nl, n, x, T, D, nnei, st);
-    else launch_fwd_t<float, __bf16, 8>(m, nl, n, x, T, D, nnei, st);
+    if (precision == DP_FP64) launch_fwd_t<double, double>(m, nl, n, x, T, D, rec, rcnt, nnei, nseg, st);
+    else if (precision == DP_FP32) launch_fwd_t<float, float>(m, nl, n, x, T, D, rec, rcnt, nnei, nseg, st);
+    else launch_fwd_t<float, __bf16>(m, nl, n, x, T, D, rec, rcnt, nnei, nseg, st);
 }
 
 void launch_emb_bwd(const dp_model *m, const dp_nlist *nl, int n, const double *x, int precision,
-                    const void *dT, double *force, double *w_atom, hipStream_t st)
+                    const void *T, const void *dD, const void *rec, const int *rcnt, double *force,
+                    double *w_atom, hipStream_t st)
 {
-    if (precision == DP_FP64) launch_bwd_t<double, 4>(m, nl, n, x, dT, force, w_atom, st);
-    else launch_bwd_t<float, 8>(m, nl, n, x, dT, force, w_atom, st);
+    if (precision == DP_FP64) launch_bwd_t<double, 4>(m, nl, n, x, T, dD, rec, rcnt, force, w_atom, st);
+    else launch_bwd_t<float, 8>(m, nl, n, x, T, dD, rec, rcnt, force, w_atom, st);
 }
 
 }  // namespace dp

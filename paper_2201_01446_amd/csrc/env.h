@@ -27,15 +27,32 @@ struct EnvArgs {
     int n_fine, n_tail;
     double h, s_max, h_tail, tail_max;
     int *flags;
+    // compacted neighbors of the forward (r_ij and the candidate slot, sel
+    // entries per atom) and their count, written by the forward, read back by
+    // the backward; or NULL
+    void *rec;
+    int *rcnt;
+    // per candidate slot dE_i/dr_ij (3 reals; cap slots per atom): the forward
+    // zeroes the slots it does not keep, the backward writes the kept ones
+    void *pg;
 };
 
-// Per-wave LDS slice.
+// What a kernel keeps per neighbor in its LDS slice.
+enum EnvMode {
+    ENV_FWD = 0,    // R_j, t_j, interval
+    ENV_BWD = 1,    // r_ij, t_j, interval, neighbor index j (R_j is recomputed from r_ij)
+    ENV_PLAIN = 2   // R_j, r_ij, (t, ds/dr, 1/r, s), interval, j for the untabulated path
+};
+
+// Per-wave LDS slice (arrays of sel entries; V4 arrays first for alignment).
 template <typename real>
 struct NbrLDS {
-    V4<real> *R;   // R_j (4 environment columns); holds r_ij during the scan
-    V4<real> *P;   // t (table offset), ds/dr, 1/r, s
-    V4<real> *Dv;  // r_ij (backward only)
-    int2 *I;       // table interval, neighbor index j
+    V4<real> *R;   // R_j (ENV_FWD, ENV_PLAIN); holds r_ij during the scan
+    V4<real> *Dv;  // r_ij (ENV_BWD, ENV_PLAIN; in ENV_BWD also the scan's slot)
+    V4<real> *P;   // t, ds/dr, 1/r, s (ENV_PLAIN)
+    real *t;       // offset of s_j from its interval's left node
+    int *th;       // table interval (bit 30: s past the table end)
+    int *j;        // neighbor index j (ENV_PLAIN) or its candidate slot (ENV_BWD)
 };
 
 template <typename real>
@@ -62,11 +79,106 @@ __device__ inline void gate(const EnvArgs &A, real r, real &w, real &dw)
 
 constexpr int kOobBit = 1 << 30;
 
+// 1/r, s = w(r)/r and ds/dr of one neighbor displacement d.
+template <typename real>
+__device__ inline void env_geom(const EnvArgs &A, const V4<real> &d, real &rinv, real &s, real &sp)
+{
+    real r = sqrt(d.x * d.x + d.y * d.y + d.z * d.z);
+    real w, dw;
+    gate<real>(A, r, w, dw);
+    rinv = (real)1 / r;
+    s = w * rinv;
+    sp = dw * rinv - s * rinv;
+}
+
 __device__ inline int s8(int v, int sh) { return (int)(signed char)((v >> sh) & 0xFF); }
+
+// Record of one compacted neighbor: r_ij and its candidate slot c (< 2^24,
+// exact in either precision's mantissa).
+__device__ inline int record_slot(float w) { return __builtin_bit_cast(int, w); }
+__device__ inline int record_slot(double w) { return (int)w; }
+template <typename real>
+__device__ inline void put_record(const EnvArgs &A, int i, int pos, double d0, double d1, double d2, int c)
+{
+    V4<real> *rec = reinterpret_cast<V4<real> *>(A.rec) + (long)i * A.sel + pos;
+    if (sizeof(real) == 4)
+        *reinterpret_cast<V4<float> *>(rec) =
+            V4<float>{(float)d0, (float)d1, (float)d2, __builtin_bit_cast(float, c)};
+    else
+        *reinterpret_cast<V4<double> *>(rec) = V4<double>{d0, d1, d2, (double)c};
+}
+// Pair gradient slot of candidate c of atom i: 4 floats (one 16-byte
+// access) or 3 doubles.
+template <typename real>
+__device__ inline real *pg_slot(void *pg, int cap, long i, int c)
+{
+    return reinterpret_cast<real *>(pg) + ((long)i * cap + c) * (sizeof(real) == 4 ? 4 : 3);
+}
+template <typename real>
+__device__ inline void put_pg(void *pg, int cap, long i, int c, real g0, real g1, real g2)
+{
+    real *g = pg_slot<real>(pg, cap, i, c);
+    if (sizeof(real) == 4) {
+        *reinterpret_cast<V4<float> *>(g) = V4<float>{(float)g0, (float)g1, (float)g2, 0.f};
+    } else {
+        g[0] = g0;
+        g[1] = g1;
+        g[2] = g2;
+    }
+}
+// Zero pair gradient for candidate slot c of atom i (not kept this step).
+template <typename real>
+__device__ inline void zero_pg(const EnvArgs &A, int i, int c)
+{
+    put_pg<real>(A.pg, A.cap, i, c, (real)0, (real)0, (real)0);
+}
+
+// Per neighbor k < nn of the slice: s, R_j, the table interval and offset
+// (and what MODE keeps); returns this lane's count of look-ups past the table.
+template <typename real, int MODE, bool TAB>
+__device__ int finish_env(const EnvArgs &A, NbrLDS<real> L, int nn, int lane)
+{
+    int oob = 0;
+    for (int k = lane; k < nn; k += 64) {
+        V4<real> d = MODE == ENV_BWD ? L.Dv[k] : L.R[k];
+        real rinv, s, sp;
+        env_geom<real>(A, d, rinv, s, sp);
+        // table interval of s (left-closed) and offset from its left node
+        int th = 0;
+        real t = 0;
+        if (!TAB) {
+        } else if (s < (real)A.s_max) {
+            int q = (int)floor(s / (real)A.h);
+            q = q > 0 ? q : 0;
+            th = q < A.n_fine - 1 ? q : A.n_fine - 1;
+            t = s - (real)th * (real)A.h;
+        } else if (A.n_tail > 0 && s < (real)A.tail_max) {
+            int q = (int)floor((s - (real)A.s_max) / (real)A.h_tail);
+            q = q > 0 ? q : 0;
+            q = q < A.n_tail - 1 ? q : A.n_tail - 1;
+            th = A.n_fine + q;
+            t = s - ((real)A.s_max + (real)q * (real)A.h_tail);
+        } else {
+            // clamped to the table end: G is constant there, so G' = 0
+            // (flag bit 30 on the interval tells the backward to drop G')
+            th = (A.n_fine + A.n_tail - 1) | kOobBit;
+            t = (real)(A.n_tail > 0 ? A.h_tail : A.h);
+            oob++;
+        }
+        if (MODE != ENV_BWD) L.R[k] = V4<real>{s, s * d.x * rinv, s * d.y * rinv, s * d.z * rinv};
+        L.t[k] = t;
+        L.th[k] = th;
+        if (MODE == ENV_PLAIN) {
+            L.Dv[k] = d;
+            L.P[k] = V4<real>{t, sp, rinv, s};
+        }
+    }
+    return oob;
+}
 
 // Neighbors of atom i within rcut, the sel nearest, into LDS; returns their
 // number (uniform over the wave).  *oob counts table look-ups past the end.
-template <typename real, bool BWD, bool TAB = true>
+template <typename real, int MODE, bool TAB = true>
 __device__ int build_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane, int &n_in_out,
                          int &oob_out)
 {
@@ -97,9 +209,11 @@ __device__ int build_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane, int 
         unsigned long long mask = __ballot(in);
         int pos = n_in + __popcll(mask & ((1ull << lane) - 1ull));
         if (in && pos < A.sel) {
-            L.R[pos] = V4<real>{(real)d0, (real)d1, (real)d2, (real)0};
-            L.I[pos] = make_int2(0, j);
+            (MODE == ENV_BWD ? L.Dv : L.R)[pos] = V4<real>{(real)d0, (real)d1, (real)d2, (real)0};
+            if (MODE != ENV_FWD) L.j[pos] = j;
+            if (MODE == ENV_FWD && A.rec) put_record<real>(A, i, pos, d0, d1, d2, k);
         }
+        if (MODE == ENV_FWD && A.pg && k < nc && !in) zero_pg<real>(A, i, k);
         n_in += __popcll(mask);
     }
     if (n_in > A.sel) {
@@ -123,53 +237,40 @@ __device__ int build_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane, int 
                 rank += less ? 1 : 0;
             }
             if (rank < A.sel) {
-                L.R[rank] = V4<real>{(real)d0, (real)d1, (real)d2, (real)0};
-                L.I[rank] = make_int2(0, j);
+                (MODE == ENV_BWD ? L.Dv : L.R)[rank] = V4<real>{(real)d0, (real)d1, (real)d2, (real)0};
+                if (MODE != ENV_FWD) L.j[rank] = j;
+                if (MODE == ENV_FWD && A.rec) put_record<real>(A, i, rank, d0, d1, d2, k);
+            } else if (MODE == ENV_FWD && A.pg) {
+                zero_pg<real>(A, i, k);   // within rcut but beyond the sel nearest
             }
         }
     }
     int nn = n_in < A.sel ? n_in : A.sel;
+    if (MODE == ENV_FWD && A.rec && lane == 0) A.rcnt[i] = nn;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    int oob = 0;
-    for (int k = lane; k < nn; k += 64) {
-        V4<real> d = L.R[k];
-        real r = sqrt(d.x * d.x + d.y * d.y + d.z * d.z);
-        real w, dw;
-        gate<real>(A, r, w, dw);
-        real rinv = (real)1 / r;
-        real s = w * rinv;
-        real sp = dw * rinv - s * rinv;
-        // table interval of s (left-closed) and offset from its left node
-        int th = 0;
-        real t = 0;
-        if (!TAB) {
-        } else if (s < (real)A.s_max) {
-            int q = (int)floor(s / (real)A.h);
-            q = q > 0 ? q : 0;
-            th = q < A.n_fine - 1 ? q : A.n_fine - 1;
-            t = s - (real)th * (real)A.h;
-        } else if (A.n_tail > 0 && s < (real)A.tail_max) {
-            int q = (int)floor((s - (real)A.s_max) / (real)A.h_tail);
-            q = q > 0 ? q : 0;
-            q = q < A.n_tail - 1 ? q : A.n_tail - 1;
-            th = A.n_fine + q;
-            t = s - ((real)A.s_max + (real)q * (real)A.h_tail);
-        } else {
-            // clamped to the table end: G is constant there, so G' = 0
-            // (flag bit 30 on the interval tells the backward to drop G')
-            th = (A.n_fine + A.n_tail - 1) | kOobBit;
-            t = (real)(A.n_tail > 0 ? A.h_tail : A.h);
-            oob++;
-        }
-        L.R[k] = V4<real>{s, s * d.x * rinv, s * d.y * rinv, s * d.z * rinv};
-        L.P[k] = V4<real>{t, sp, rinv, s};
-        if (BWD) L.Dv[k] = d;
-        L.I[k].x = th;
-    }
+    oob_out = finish_env<real, MODE, TAB>(A, L, nn, lane);
     n_in_out = n_in;
-    oob_out = oob;
+    return nn;
+}
+
+// The backward's neighbors of atom i: read back the forward's records (no
+// scan of the skin list), then the same per-neighbor quantities.
+template <typename real>
+__device__ int load_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane)
+{
+    int nn = A.rcnt[i];
+    const V4<real> *rec = reinterpret_cast<const V4<real> *>(A.rec) + (long)i * A.sel;
+    for (int k = lane; k < nn; k += 64) {
+        V4<real> r = rec[k];
+        L.Dv[k] = V4<real>{r.x, r.y, r.z, (real)0};
+        L.j[k] = record_slot(r.w);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    finish_env<real, ENV_BWD, true>(A, L, nn, lane);
     return nn;
 }
 
@@ -185,22 +286,32 @@ __device__ inline void record_flags(const EnvArgs &A, int lane, int n_in, int oo
     }
 }
 
+// Bytes of the per-neighbor arrays of one wave's slice (a multiple of the
+// V4 size, so slices and what follows them stay aligned).
 template <typename real>
-constexpr int lds_bytes_per_wave(int sel, bool bwd)
+constexpr int nbr_lds_bytes(int sel, int mode)
 {
-    return sel * (int)(sizeof(V4<real>) * (bwd ? 3 : 2) + sizeof(int2)) +
-           (bwd ? 0 : 4 * kM * (int)sizeof(real));
+    int v4 = mode == ENV_PLAIN ? 3 : 1;
+    int ints = mode == ENV_FWD ? 1 : 2;
+    int b = sel * (v4 * (int)sizeof(V4<real>) + (int)sizeof(real) + ints * 4);
+    constexpr int al = (int)sizeof(V4<real>);
+    return (b + al - 1) / al * al;
 }
 
 template <typename real>
-__device__ NbrLDS<real> carve(char *base, int sel, bool bwd, real *&Tl)
+__device__ NbrLDS<real> carve(char *base, int sel, int mode)
 {
     NbrLDS<real> L;
-    L.R = reinterpret_cast<V4<real> *>(base);
-    L.P = L.R + sel;
-    L.Dv = bwd ? L.P + sel : nullptr;
-    L.I = reinterpret_cast<int2 *>(bwd ? L.Dv + sel : L.P + sel);
-    Tl = reinterpret_cast<real *>(L.I + sel);
+    V4<real> *v = reinterpret_cast<V4<real> *>(base);
+    L.R = mode != ENV_BWD ? v : nullptr;
+    if (mode != ENV_BWD) v += sel;
+    L.Dv = mode != ENV_FWD ? v : nullptr;
+    if (mode != ENV_FWD) v += sel;
+    L.P = mode == ENV_PLAIN ? v : nullptr;
+    if (mode == ENV_PLAIN) v += sel;
+    L.t = reinterpret_cast<real *>(v);
+    L.th = reinterpret_cast<int *>(L.t + sel);
+    L.j = mode != ENV_FWD ? L.th + sel : nullptr;
     return L;
 }
 
@@ -228,6 +339,9 @@ inline EnvArgs make_env_args(const dp_model *m, const dp_nlist *nl, const double
     A.h_tail = m->tab.h_tail;
     A.tail_max = m->tab.tail_max;
     A.flags = nl->flags;
+    A.rec = nullptr;
+    A.rcnt = nullptr;
+    A.pg = nullptr;
     return A;
 }
 

@@ -16,6 +16,7 @@
 // the caller's (unwrapped) coordinates.
 
 #include "dp_internal.h"
+#include "env.h"
 
 #include <cmath>
 #include <cstdio>
@@ -97,7 +98,8 @@ __device__ void bitonic_sort(unsigned long long *keys, int P)
 }
 
 __device__ void finish_atom(int i, int cnt, int cap, unsigned long long *keys, const int *wrap,
-                            int ki_packed, int *out_cnt, int *out_nei, int *out_shift, int *flags, int joff)
+                            int ki_packed, int *out_cnt, int *out_nei, int *out_shift, float *out_dist,
+                            int *flags, int joff)
 {
     int lane = threadIdx.x;
     if (cnt > cap) {
@@ -122,6 +124,7 @@ __device__ void finish_atom(int i, int cnt, int cap, unsigned long long *keys, c
             kjz = (int)(signed char)((kj >> 16) & 0xFF);
         out_nei[(long)i * cap + t] = j + joff;
         out_shift[(long)i * cap + t] = pack_shift(sx + kix - kjx, sy + kiy - kjy, sz + kiz - kjz);
+        out_dist[(long)i * cap + t] = __uint_as_float((unsigned)(key >> 32));
     }
     if (lane == 0) out_cnt[i] = cnt;
 }
@@ -132,7 +135,7 @@ __global__ void __launch_bounds__(64) k_candidates_cells(
     double Lz, int ncx, int ncy, int ncz, int Rx, int Ry, int Rz, int cellcap,
     const int *__restrict__ cell_cnt, const int *__restrict__ cell_atoms, double rcs2, int cap,
     int *__restrict__ out_cnt, int *__restrict__ out_nei, int *__restrict__ out_shift,
-    int *__restrict__ flags, int joff)
+    float *__restrict__ out_dist, int *__restrict__ flags, int joff)
 {
     HIP_DYNAMIC_SHARED(unsigned long long, keys)
     __shared__ int count;
@@ -170,7 +173,7 @@ __global__ void __launch_bounds__(64) k_candidates_cells(
         }
     }
     __syncthreads();
-    finish_atom(i, count, cap, keys, wrap, wrap[i], out_cnt, out_nei, out_shift, flags, joff);
+    finish_atom(i, count, cap, keys, wrap, wrap[i], out_cnt, out_nei, out_shift, out_dist, flags, joff);
 }
 
 // Open boundary: brute force over all atoms (for clusters of modest size).
@@ -179,6 +182,7 @@ __global__ void __launch_bounds__(64) k_candidates_open(int n, const double *__r
                                                         int cap, int *__restrict__ out_cnt,
                                                         int *__restrict__ out_nei,
                                                         int *__restrict__ out_shift,
+                                                        float *__restrict__ out_dist,
                                                         int *__restrict__ flags, int joff)
 {
     HIP_DYNAMIC_SHARED(unsigned long long, keys)
@@ -201,7 +205,7 @@ __global__ void __launch_bounds__(64) k_candidates_open(int n, const double *__r
         }
     }
     __syncthreads();
-    finish_atom(i, count, cap, keys, nullptr, 0, out_cnt, out_nei, out_shift, flags, joff);
+    finish_atom(i, count, cap, keys, nullptr, 0, out_cnt, out_nei, out_shift, out_dist, flags, joff);
 }
 
 }  // namespace
@@ -224,7 +228,8 @@ dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, c
     if (reset_flags) launch_fill_zero_int(nl->flags, kNumFlags, st);
     if (!nl->periodic) {
         hipLaunchKernelGGL(k_candidates_open, dim3(n), dim3(64), lds, st, n, x, types, rcs2, nl->cap,
-                           nl->cnt, nl->nei, nl->shift, nl->flags, 0);
+                           nl->cnt, nl->nei, nl->shift, nl->dist, nl->flags, 0);
+        launch_reverse(nl, 0, n, st);
         return DP_OK;
     }
     long ncell = (long)nl->nc[0] * nl->nc[1] * nl->nc[2];
@@ -243,7 +248,8 @@ dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, c
                        nl->wpos, nl->wrap, nl->L[0], nl->L[1],
                        nl->L[2], nl->nc[0], nl->nc[1], nl->nc[2], R[0], R[1], R[2], nl->cellcap,
                        nl->cell_cnt, nl->cell_atoms, rcs2, nl->cap, nl->cnt, nl->nei, nl->shift,
-                       nl->flags, 0);
+                       nl->dist, nl->flags, 0);
+    launch_reverse(nl, 0, n, st);
     return DP_OK;
 }
 
@@ -257,9 +263,10 @@ dp_status launch_build_nlist_range(dp_nlist *nl, const double *x, int off, int n
     long cap = nl->cap;
     const double *xr = x + 3L * off;
     int *cnt = nl->cnt + off, *nei = nl->nei + off * cap, *shift = nl->shift + off * cap;
+    float *dist = nl->dist + off * cap;
     if (!L) {
         hipLaunchKernelGGL(k_candidates_open, dim3(n), dim3(64), lds, st, n, xr, (const int *)nullptr, rcs2,
-                           nl->cap, cnt, nei, shift, nl->flags, off);
+                           nl->cap, cnt, nei, shift, dist, nl->flags, off);
         return DP_OK;
     }
     int nc[3], R[3];
@@ -277,7 +284,7 @@ dp_status launch_build_nlist_range(dp_nlist *nl, const double *x, int off, int n
                        nl->cell_atoms, nl->flags);
     hipLaunchKernelGGL(k_candidates_cells, dim3(n), dim3(64), lds, st, n, nl->wpos + 3L * off, nl->wrap + off, L[0],
                        L[1], L[2], nc[0], nc[1], nc[2], R[0], R[1], R[2], nl->cellcap, nl->cell_cnt, nl->cell_atoms,
-                       rcs2, nl->cap, cnt, nei, shift, nl->flags, off);
+                       rcs2, nl->cap, cnt, nei, shift, dist, nl->flags, off);
     return DP_OK;
 }
 
@@ -330,6 +337,171 @@ void launch_segment_reduce(int nreq, const int *offsets, const double *e_atom, c
 void launch_expand_boxes(int nreq, const int *offsets, const double *Lreq, double *atomL, hipStream_t st)
 {
     hipLaunchKernelGGL(k_expand_boxes, dim3(nreq), dim3(256), 0, st, offsets, Lreq, atomL);
+}
+
+
+namespace {
+
+__global__ void k_fill_short(short *p, long n, short v)
+{
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__device__ inline int neg_shift(int v)
+{
+    int a = (int)(signed char)(v & 0xFF), b = (int)(signed char)((v >> 8) & 0xFF),
+        c = (int)(signed char)((v >> 16) & 0xFF);
+    return pack_shift(-a, -b, -c);
+}
+
+// rev[i][c] = the slot of (i, -shift) in the list of j = nei[i][c], found
+// by distance in j's sorted list (a few float ulps of slack: j computed the
+// same distance from the other side), then a scan of the equal-distance
+// window.  The search starts at c (neighborhoods are alike, so the rank of
+// r_ij in both lists is similar) and gallops outward.  Each pair is searched
+// once, from its lower-indexed side (self-images: from the side with the
+// larger shift code), and both slots are written.  -1 when j's list lacks i,
+// which happens only at the edge of the skin, far outside rcut.  One
+// 64-thread block per atom.
+__global__ void __launch_bounds__(64) k_reverse(int off, int cap, const int *__restrict__ cnt,
+                                                const int *__restrict__ nei, const int *__restrict__ shift,
+                                                const float *__restrict__ dist, short *__restrict__ rev)
+{
+    int i = off + blockIdx.x;
+    int nc = cnt[i];
+    for (int c = threadIdx.x; c < nc; c += 64) {
+        long ic = (long)i * cap + c;
+        int j = nei[ic];
+        int sh = shift[ic];
+        int want = neg_shift(sh);
+        if (j < i || (j == i && sh < want)) continue;   // the other side searches
+        float r = dist[ic];
+        unsigned rb = __float_as_uint(r);
+        float lo = __uint_as_float(rb > 8u ? rb - 8u : 0u), hi = __uint_as_float(rb + 8u);
+        const float *dj = dist + (long)j * cap;
+        int ncj = cnt[j];
+        // first index a with dj[a] >= lo: gallop from min(c, ncj - 1), then bisect
+        int a, b;
+        int p = c < ncj ? c : ncj - 1;
+        if (ncj == 0) {
+            a = b = 0;
+        } else if (dj[p] < lo) {
+            int step = 1;
+            a = p + 1;
+            b = p + 1;
+            while (b < ncj && dj[b] < lo) {
+                a = b + 1;
+                b += step;
+                step <<= 1;
+            }
+            if (b > ncj) b = ncj;
+        } else {
+            int step = 1;
+            b = p;
+            a = p - 1;
+            while (a >= 0 && dj[a] >= lo) {
+                b = a;
+                a -= step;
+                step <<= 1;
+            }
+            a = a < 0 ? 0 : a + 1;
+        }
+        while (a < b) {
+            int mid = (a + b) >> 1;
+            if (dj[mid] < lo) a = mid + 1;
+            else b = mid;
+        }
+        int found = -1;
+        for (int t = a; t < ncj && dj[t] <= hi; t++) {
+            long jt = (long)j * cap + t;
+            if (nei[jt] == i && shift[jt] == want) {
+                found = t;
+                break;
+            }
+        }
+        rev[ic] = (short)found;
+        if (found >= 0) rev[(long)j * cap + found] = (short)c;
+    }
+}
+
+// One 64-lane wave per atom, lanes over its candidates, four candidates per
+// lane in flight (their indices first, then their pair gradients).
+template <typename real>
+__device__ inline void add_pg(const real *p, double &f0, double &f1, double &f2)
+{
+    if (sizeof(real) == 4) {
+        V4<float> g = *reinterpret_cast<const V4<float> *>(p);
+        f0 += (double)g.x;
+        f1 += (double)g.y;
+        f2 += (double)g.z;
+    } else {
+        f0 += (double)p[0];
+        f1 += (double)p[1];
+        f2 += (double)p[2];
+    }
+}
+
+template <typename real>
+__global__ void __launch_bounds__(256) k_force_gather(int n, int cap, const int *__restrict__ cnt,
+                                                      const int *__restrict__ nei, const short *__restrict__ rev,
+                                                      const real *__restrict__ pg, double *__restrict__ force)
+{
+    constexpr int ST = sizeof(real) == 4 ? 4 : 3;   // reals per pair-gradient slot
+    int lane = threadIdx.x & 63;
+    int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    int nc = cnt[i];
+    const int *ni = nei + (long)i * cap;
+    const short *ri = rev + (long)i * cap;
+    double f0 = 0, f1 = 0, f2 = 0;
+    for (int c0 = 0; c0 < nc; c0 += 256) {
+        long off[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            int c = c0 + 64 * u + lane;
+            int r = c < nc ? ri[c] : -1;
+            off[u] = r < 0 ? -1 : ((long)ni[c] * cap + r) * ST;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (off[u] >= 0) add_pg<real>(pg + off[u], f0, f1, f2);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        f0 += __shfl_xor(f0, o);
+        f1 += __shfl_xor(f1, o);
+        f2 += __shfl_xor(f2, o);
+    }
+    if (lane == 0) {
+        force[3 * i] -= f0;
+        force[3 * i + 1] -= f1;
+        force[3 * i + 2] -= f2;
+    }
+}
+
+}  // namespace
+
+void launch_reverse(dp_nlist *nl, int off, int n, hipStream_t st)
+{
+    if (n <= 0) return;
+    // every slot starts at -1: a pair is searched from one side only, so a
+    // slot that no search writes (j's list lacks i) must already read -1
+    long m = (long)n * nl->cap;
+    hipLaunchKernelGGL(k_fill_short, dim3(div_up(m, 256)), dim3(256), 0, st, nl->rev + (long)off * nl->cap, m,
+                       (short)-1);
+    hipLaunchKernelGGL(k_reverse, dim3(n), dim3(64), 0, st, off, nl->cap, nl->cnt, nl->nei, nl->shift,
+                       nl->dist, nl->rev);
+}
+
+void launch_force_gather(const dp_nlist *nl, int n, int precision, double *force, hipStream_t st)
+{
+    if (n <= 0) return;
+    if (precision == DP_FP64)
+        hipLaunchKernelGGL(k_force_gather<double>, dim3(div_up(n, 4)), dim3(256), 0, st, n, nl->cap, nl->cnt,
+                           nl->nei, nl->rev, (const double *)nl->pg, force);
+    else
+        hipLaunchKernelGGL(k_force_gather<float>, dim3(div_up(n, 4)), dim3(256), 0, st, n, nl->cap, nl->cnt,
+                           nl->nei, nl->rev, (const float *)nl->pg, force);
 }
 
 }  // namespace dp

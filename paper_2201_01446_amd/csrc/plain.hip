@@ -46,11 +46,10 @@ __global__ void __launch_bounds__(256) k_plain_env(int natoms, EnvArgs A, real *
     char *smem = reinterpret_cast<char *>(smem_raw);
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int i = blockIdx.x * (blockDim.x >> 6) + wave;
-    real *Tl;
-    NbrLDS<real> L = carve<real>(smem + wave * lds_bytes_per_wave<real>(A.sel, true), A.sel, true, Tl);
+    NbrLDS<real> L = carve<real>(smem + wave * nbr_lds_bytes<real>(A.sel, ENV_PLAIN), A.sel, ENV_PLAIN);
     bool live = i < natoms;
     int nn = 0, n_in = 0, oob = 0;
-    if (live) nn = build_env<real, true, false>(i, A, L, lane, n_in, oob);
+    if (live) nn = build_env<real, ENV_PLAIN, false>(i, A, L, lane, n_in, oob);
     __syncthreads();
     if (!live) return;
     record_flags<real>(A, lane, n_in, 0);
@@ -63,7 +62,7 @@ __global__ void __launch_bounds__(256) k_plain_env(int natoms, EnvArgs A, real *
             R_out[row] = L.R[k];
             P_out[row] = P;
             D_out[row] = L.Dv[k];
-            j_out[row] = L.I[k].y;
+            j_out[row] = L.j[k];
         } else {
             // a padded row: s = 0 and R = 0, still evaluated by the net
             s_out[row] = 0;
@@ -310,7 +309,7 @@ dp_status plain_forward(const dp_model *m, dp_nlist *nl, int n, const double *x,
     EmbW<real> ew = emb_weights<real>(m);
     EnvArgs A = make_env_args(m, nl, x);
     int wpb = 4;
-    size_t lds = (size_t)wpb * lds_bytes_per_wave<real>(A.sel, true);
+    size_t lds = (size_t)wpb * nbr_lds_bytes<real>(A.sel, ENV_PLAIN);
     DP_TIMED("plain_env", st,
              hipLaunchKernelGGL((k_plain_env<real>), dim3(div_up(n, wpb)), dim3(64 * wpb), lds, st, n, A, w.s, w.R,
                                 w.P, w.Dv, w.j, nnei));

@@ -255,16 +255,27 @@ def test_cu108k_sampled(P, model, cu_cfg, cu_params, otab, precision):
     assert st["table_oob"] == 0 and st["cap_overflow"] == 0
 
 
-@pytest.mark.parametrize("precision", [2, 1])
-def test_cu1m_mixed_sampled(P, model, cu_cfg, cu_params, otab, precision):
-    """1,048,576-atom copper (64^3 cells, sigma 0.08 A), mixed BF16 and FP32:
-    sampled per-atom energies and forces against the FP64 oracle."""
+@pytest.fixture(scope="module")
+def cu1m(cu_cfg, cu_params, otab):
+    """1,048,576-atom copper (64^3 cells, sigma 0.08 A) and oracle values at
+    4,096 random atoms (E_i) and 512 random atoms (forces), from cut-outs."""
+    from sampling import LocalSampler
     x, box = synth.copper(64, 0.08, synth.SEED_CFG[3])
-    got, nl = run(P, model, x, box, precision)
+    s = LocalSampler(cu_cfg, cu_params, otab, x, box)
     rng = np.random.default_rng(3)
-    e_idx = rng.choice(len(x), 64, replace=False)
-    f_idx = rng.choice(len(x), 8, replace=False)
-    e_ref, F_ref = sampled_reference(cu_cfg, cu_params, otab, x, box, e_idx, f_idx)
+    e_idx = rng.choice(len(x), 4096, replace=False)
+    f_idx = rng.choice(len(x), 512, replace=False)
+    e_ref = np.array([s.energy(int(k)) for k in e_idx])
+    F_ref = np.array([s.force(int(k)) for k in f_idx])
+    return x, box, e_idx, f_idx, e_ref, F_ref
+
+
+@pytest.mark.parametrize("precision", [2, 1])
+def test_cu1m_mixed_sampled(P, model, cu1m, precision):
+    """1M atoms in mixed BF16 and in FP32: sampled per-atom energies and
+    forces against the FP64 oracle."""
+    x, box, e_idx, f_idx, e_ref, F_ref = cu1m
+    got, nl = run(P, model, x, box, precision)
     dEi = np.max(np.abs(got["e_atom"][e_idx] - e_ref))
     eF = np.sqrt(np.mean((got["F"][f_idx] - F_ref) ** 2))
     Fs = np.sqrt(np.mean(F_ref ** 2))
@@ -273,3 +284,15 @@ def test_cu1m_mixed_sampled(P, model, cu_cfg, cu_params, otab, precision):
     assert eF <= 1e-3 and eF <= (1e-3 if precision == 2 else 1e-4) * Fs
     st = nl.stats()
     assert st["table_oob"] == 0 and st["cap_overflow"] == 0
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_forces_deterministic(P, model, precision):
+    """Forces are gathered per atom in a fixed order (no atomics): two runs
+    give bitwise-identical results in every precision."""
+    x, box = synth.copper(6, 0.1, 71)
+    a, _ = run(P, model, x, box, precision)
+    b, _ = run(P, model, x, box, precision)
+    np.testing.assert_array_equal(a["F"], b["F"])
+    np.testing.assert_array_equal(a["W"], b["W"])
+    assert a["E"][0] == b["E"][0]

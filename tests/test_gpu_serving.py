@@ -73,10 +73,12 @@ def test_batch_fp64_vs_oracle_and_alone(P, model, cu_cfg, cu_params, table):
         assert abs(r["E"] - ref["E"]) <= 1e-10 * abs(ref["E"])
         assert np.max(np.abs(r["F"] - ref["F"])) <= 1e-10 * Fs
         assert np.max(np.abs(r["W"] - ref["W"])) <= 1e-10 * Ws
+        # every sum over a request runs in an order fixed by the request itself
+        # (forces are gathered, not scattered): alone and in the mix agree exactly
         alone, _ = run_batch(P, model, [(x, box)], P.FP64, batch=batch)
-        assert abs(alone[0]["E"] - r["E"]) <= 1e-13 * abs(r["E"])
-        assert np.max(np.abs(alone[0]["F"] - r["F"])) <= 1e-13 * Fs
-        assert np.max(np.abs(alone[0]["W"] - r["W"])) <= 1e-13 * Ws
+        assert alone[0]["E"] == r["E"]
+        np.testing.assert_array_equal(alone[0]["F"], r["F"])
+        np.testing.assert_array_equal(alone[0]["W"], r["W"])
     st = batch.stats()
     assert st["sel_overflow"] == 0 and st["cap_overflow"] == 0
 
@@ -137,11 +139,11 @@ def test_batch_argument_errors(P, model):
 
 
 def test_server_closed_loop_and_poisson(P, model):
-    """The server's results equal each request computed alone (FP32; forces
-    up to the order of FP64 atomic sums), with several batches in flight."""
+    """The server's results equal each request computed alone, bit for bit
+    (FP32), with several batches in flight."""
     from paper_2201_01446_amd.serve import Server, poisson_arrivals
     reqs = [r[:2] for r in synth.serving_stream(24, 32, 3000, seed=synth.SEED_SERVING)]
-    srv = Server(model, P.FP32, slots=3, hbm_budget=3 * 250 << 20)
+    srv = Server(model, P.FP32, slots=3, hbm_budget=3 * 400 << 20)
     assert srv.slot_atoms >= 3000
     res, st = srv.run(reqs)
     print("closed loop:", st)
@@ -149,12 +151,13 @@ def test_server_closed_loop_and_poisson(P, model):
     for k in range(len(reqs)):
         alone, _ = run_batch(P, model, [reqs[k]], P.FP32)
         r, a = res[k], alone[0]
-        assert abs(r["E"] - a["E"]) <= 1e-12 * abs(a["E"])
-        assert np.max(np.abs(r["F"] - a["F"])) <= 1e-9 * np.max(np.abs(a["F"])) + 1e-12
-        assert np.max(np.abs(r["W"] - a["W"])) <= 1e-9 * np.max(np.abs(a["W"])) + 1e-12
+        assert r["E"] == a["E"]
+        np.testing.assert_array_equal(r["F"], a["F"])
+        np.testing.assert_array_equal(r["W"], a["W"])
     rate = 0.7 * len(reqs) / st["wall_s"]
     res2, st2 = srv.run(reqs, poisson_arrivals(len(reqs), rate, seed=3))
     print("poisson:", st2)
     for k in range(len(reqs)):
-        assert abs(res2[k]["E"] - res[k]["E"]) <= 1e-12 * abs(res[k]["E"])
+        assert res2[k]["E"] == res[k]["E"]
+        np.testing.assert_array_equal(res2[k]["F"], res[k]["F"])
     assert st2["p99_ms"] >= st2["p50_ms"] > 0
