@@ -154,6 +154,16 @@ dp_status step_check(const char *name, hipStream_t st);
 inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
 inline long round_up(long a, long b) { return (a + b - 1) / b * b; }
 
+// XCD-aware work order.  The dispatcher deals the blocks of a grid round-robin
+// over the 8 XCDs (each with its own L2), so block b runs on XCD b % 8.  A
+// kernel whose neighboring items share data (atoms and their neighbors) gives
+// XCD x the contiguous item range [x G/8, (x+1) G/8) instead; the grid is
+// padded to a multiple of 8 (xcd_grid) and items past the real count exit.
+// Only locality depends on the dealing order, never correctness.
+constexpr int kXcd = 8;
+inline int xcd_grid(long nblocks) { return (int)round_up(nblocks, kXcd); }
+__device__ inline int xcd_item(int b, int grid) { return (b % kXcd) * (grid / kXcd) + b / kXcd; }
+
 // ------------------------------------------------------------- launchers
 // (defined in the kernel translation units; all enqueue on `st`)
 void launch_fill_zero(double *p, long n, hipStream_t st);

@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(256) k_emb_fwd(int natoms, EnvArgs A, const re
     HIP_DYNAMIC_SHARED(uint4, smem_raw)   // 16-byte aligned
     char *base = reinterpret_cast<char *>(smem_raw);
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int i = blockIdx.x * (blockDim.x >> 6) + wave;
+    int i = xcd_item(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave;
     base += wave * fwd_lds_bytes<real>(A.sel);
     NbrLDS<real> L = carve<real>(base, A.sel, ENV_FWD);
     char *p = base + nbr_lds_bytes<real>(A.sel, ENV_FWD);
@@ -303,7 +303,7 @@ __global__ void __launch_bounds__(256) k_emb_bwd(int natoms, EnvArgs A, const re
     HIP_DYNAMIC_SHARED(uint4, smem_raw)   // 16-byte aligned
     char *base = reinterpret_cast<char *>(smem_raw);
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int i = blockIdx.x * (blockDim.x >> 6) + wave;
+    int i = xcd_item(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave;
     base += wave * bwd_lds_bytes<real>(A.sel);
     NbrLDS<real> L = carve<real>(base, A.sel, ENV_BWD);
     char *p = base + nbr_lds_bytes<real>(A.sel, ENV_BWD);
@@ -495,7 +495,7 @@ static void launch_fwd_t(const dp_model *m, const dp_nlist *nl, int n, const dou
     const real *tab = std::is_same<real, double>::value ? (const real *)m->tab64 : (const real *)m->tab32;
     int wpb = 4;
     size_t lds = (size_t)wpb * fwd_lds_bytes<real>(A.sel);
-    hipLaunchKernelGGL((k_emb_fwd<real, TD>), dim3(div_up(n, wpb)), dim3(64 * wpb), lds, st, n, A, tab,
+    hipLaunchKernelGGL((k_emb_fwd<real, TD>), dim3(xcd_grid(div_up(n, wpb))), dim3(64 * wpb), lds, st, n, A, tab,
                        (real)m->cfg.desc_scale, (real *)T, (TD *)D, nnei, nseg);
 }
 
@@ -511,7 +511,7 @@ static void launch_bwd_t(const dp_model *m, const dp_nlist *nl, int n, const dou
     const real *tab = std::is_same<real, double>::value ? (const real *)m->tab64 : (const real *)m->tab32;
     int wpb = 4;
     size_t lds = (size_t)wpb * bwd_lds_bytes<real>(A.sel);
-    hipLaunchKernelGGL((k_emb_bwd<real, CPL>), dim3(div_up(n, wpb)), dim3(64 * wpb), lds, st, n, A, tab,
+    hipLaunchKernelGGL((k_emb_bwd<real, CPL>), dim3(xcd_grid(div_up(n, wpb))), dim3(64 * wpb), lds, st, n, A, tab,
                        (real)m->cfg.desc_scale, (const real *)T, (const real *)dD, force, w_atom);
 }
 

@@ -139,7 +139,8 @@ __global__ void __launch_bounds__(64) k_candidates_cells(
 {
     HIP_DYNAMIC_SHARED(unsigned long long, keys)
     __shared__ int count;
-    int i = blockIdx.x;
+    int i = xcd_item(blockIdx.x, gridDim.x);
+    if (i >= n) return;   // the whole (one-wave) block
     int lane = threadIdx.x;
     if (lane == 0) count = 0;
     __syncthreads();
@@ -187,7 +188,8 @@ __global__ void __launch_bounds__(64) k_candidates_open(int n, const double *__r
 {
     HIP_DYNAMIC_SHARED(unsigned long long, keys)
     __shared__ int count;
-    int i = blockIdx.x;
+    int i = xcd_item(blockIdx.x, gridDim.x);
+    if (i >= n) return;   // the whole (one-wave) block
     int lane = threadIdx.x;
     if (lane == 0) {
         count = 0;
@@ -227,7 +229,7 @@ dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, c
     (void)m;
     if (reset_flags) launch_fill_zero_int(nl->flags, kNumFlags, st);
     if (!nl->periodic) {
-        hipLaunchKernelGGL(k_candidates_open, dim3(n), dim3(64), lds, st, n, x, types, rcs2, nl->cap,
+        hipLaunchKernelGGL(k_candidates_open, dim3(xcd_grid(n)), dim3(64), lds, st, n, x, types, rcs2, nl->cap,
                            nl->cnt, nl->nei, nl->shift, nl->dist, nl->flags, 0);
         launch_reverse(nl, 0, n, st);
         return DP_OK;
@@ -244,7 +246,7 @@ dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, c
         R[a] = (int)ceil(nl->rc_build / c - 1e-12);
         if (R[a] > 2) return fail(DP_ERR_UNSUPPORTED, "box edge shorter than (rcut + skin) / 2");
     }
-    hipLaunchKernelGGL(k_candidates_cells, dim3(n), dim3(64), lds, st, n,
+    hipLaunchKernelGGL(k_candidates_cells, dim3(xcd_grid(n)), dim3(64), lds, st, n,
                        nl->wpos, nl->wrap, nl->L[0], nl->L[1],
                        nl->L[2], nl->nc[0], nl->nc[1], nl->nc[2], R[0], R[1], R[2], nl->cellcap,
                        nl->cell_cnt, nl->cell_atoms, rcs2, nl->cap, nl->cnt, nl->nei, nl->shift,
@@ -265,7 +267,7 @@ dp_status launch_build_nlist_range(dp_nlist *nl, const double *x, int off, int n
     int *cnt = nl->cnt + off, *nei = nl->nei + off * cap, *shift = nl->shift + off * cap;
     float *dist = nl->dist + off * cap;
     if (!L) {
-        hipLaunchKernelGGL(k_candidates_open, dim3(n), dim3(64), lds, st, n, xr, (const int *)nullptr, rcs2,
+        hipLaunchKernelGGL(k_candidates_open, dim3(xcd_grid(n)), dim3(64), lds, st, n, xr, (const int *)nullptr, rcs2,
                            nl->cap, cnt, nei, shift, dist, nl->flags, off);
         return DP_OK;
     }
@@ -282,7 +284,7 @@ dp_status launch_build_nlist_range(dp_nlist *nl, const double *x, int off, int n
     hipLaunchKernelGGL(k_bin, dim3(div_up(n, 256)), dim3(256), 0, st, n, xr, (const int *)nullptr, L[0], L[1], L[2],
                        nc[0], nc[1], nc[2], nl->cellcap, nl->wpos + 3L * off, nl->wrap + off, nl->cell_cnt,
                        nl->cell_atoms, nl->flags);
-    hipLaunchKernelGGL(k_candidates_cells, dim3(n), dim3(64), lds, st, n, nl->wpos + 3L * off, nl->wrap + off, L[0],
+    hipLaunchKernelGGL(k_candidates_cells, dim3(xcd_grid(n)), dim3(64), lds, st, n, nl->wpos + 3L * off, nl->wrap + off, L[0],
                        L[1], L[2], nc[0], nc[1], nc[2], R[0], R[1], R[2], nl->cellcap, nl->cell_cnt, nl->cell_atoms,
                        rcs2, nl->cap, cnt, nei, shift, dist, nl->flags, off);
     return DP_OK;
@@ -364,11 +366,13 @@ __device__ inline int neg_shift(int v)
 // larger shift code), and both slots are written.  -1 when j's list lacks i,
 // which happens only at the edge of the skin, far outside rcut.  One
 // 64-thread block per atom.
-__global__ void __launch_bounds__(64) k_reverse(int off, int cap, const int *__restrict__ cnt,
+__global__ void __launch_bounds__(64) k_reverse(int off, int n, int cap, const int *__restrict__ cnt,
                                                 const int *__restrict__ nei, const int *__restrict__ shift,
                                                 const float *__restrict__ dist, short *__restrict__ rev)
 {
-    int i = off + blockIdx.x;
+    int ib = xcd_item(blockIdx.x, gridDim.x);
+    if (ib >= n) return;
+    int i = off + ib;
     int nc = cnt[i];
     for (int c = threadIdx.x; c < nc; c += 64) {
         long ic = (long)i * cap + c;
@@ -449,7 +453,7 @@ __global__ void __launch_bounds__(256) k_force_gather(int n, int cap, const int 
 {
     constexpr int ST = sizeof(real) == 4 ? 4 : 3;   // reals per pair-gradient slot
     int lane = threadIdx.x & 63;
-    int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    int i = xcd_item(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     if (i >= n) return;
     int nc = cnt[i];
     const int *ni = nei + (long)i * cap;
@@ -489,7 +493,7 @@ void launch_reverse(dp_nlist *nl, int off, int n, hipStream_t st)
     long m = (long)n * nl->cap;
     hipLaunchKernelGGL(k_fill_short, dim3(div_up(m, 256)), dim3(256), 0, st, nl->rev + (long)off * nl->cap, m,
                        (short)-1);
-    hipLaunchKernelGGL(k_reverse, dim3(n), dim3(64), 0, st, off, nl->cap, nl->cnt, nl->nei, nl->shift,
+    hipLaunchKernelGGL(k_reverse, dim3(xcd_grid(n)), dim3(64), 0, st, off, n, nl->cap, nl->cnt, nl->nei, nl->shift,
                        nl->dist, nl->rev);
 }
 
@@ -497,10 +501,10 @@ void launch_force_gather(const dp_nlist *nl, int n, int precision, double *force
 {
     if (n <= 0) return;
     if (precision == DP_FP64)
-        hipLaunchKernelGGL(k_force_gather<double>, dim3(div_up(n, 4)), dim3(256), 0, st, n, nl->cap, nl->cnt,
+        hipLaunchKernelGGL(k_force_gather<double>, dim3(xcd_grid(div_up(n, 4))), dim3(256), 0, st, n, nl->cap, nl->cnt,
                            nl->nei, nl->rev, (const double *)nl->pg, force);
     else
-        hipLaunchKernelGGL(k_force_gather<float>, dim3(div_up(n, 4)), dim3(256), 0, st, n, nl->cap, nl->cnt,
+        hipLaunchKernelGGL(k_force_gather<float>, dim3(xcd_grid(div_up(n, 4))), dim3(256), 0, st, n, nl->cap, nl->cnt,
                            nl->nei, nl->rev, (const float *)nl->pg, force);
 }
 
