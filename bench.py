@@ -71,13 +71,17 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-strides", action="store_true", help="skip the table-stride sweep")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the optimization ladder")
+    ap.add_argument("--ablation-steps", type=int, default=10)
+    ap.add_argument("--stride-steps", type=int, default=20)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one elementwise negation over this many MiB (reads and writes it once): "
                          "the calibration of HBM byte counters")
     return ap.parse_args()
 
 
-def run_nve(P, model, x0, v0, box, steps, warmup, precision, mode=0):
+def run_nve(P, model, x0, v0, box, steps, warmup, precision, mode=0, keep=False):
     import torch
     x = torch.tensor(x0, dtype=torch.float64, device="cuda")
     v = torch.tensor(v0, dtype=torch.float64, device="cuda")
@@ -100,7 +104,10 @@ def run_nve(P, model, x0, v0, box, steps, warmup, precision, mode=0):
     _lib.timers_enable(False)
     kern = _lib.timers_read()
     ms = t0.elapsed_time(t1)
-    return dict(ms=ms, wall=wall, thermo=th.cpu().numpy(), kernels=kern, x=x, nl=nl)
+    out = dict(ms=ms, wall=wall, thermo=th.cpu().numpy(), kernels=kern)
+    if keep:   # the list owns the scratch (tens of GB for the plain path): kept only on request
+        out.update(x=x, nl=nl)
+    return out
 
 
 def main():
@@ -128,7 +135,7 @@ def main():
     N = len(x0)
     K, W = args.steps, args.warmup
 
-    res32 = run_nve(P, model, x0, v0, box, K, W, P.FP32)
+    res32 = run_nve(P, model, x0, v0, box, K, W, P.FP32, keep=True)
     res64 = None if args.no_fp64 else run_nve(P, model, x0, v0, box, K, W, P.FP64)
     resbf = run_nve(P, model, x0, v0, box, K, W, P.MIXED_BF16)
     # the plain (untabulated, padded, materialised) path: same MD protocol,
@@ -231,11 +238,89 @@ def main():
         out[name] = {"value": round(vp, 1), "ms_per_step": round(res["ms"] / Kp, 4), "steps": Kp,
                      "kernels": {k: round(v[0] / max(v[1], 1), 4) for k, v in res["kernels"].items()},
                      "speedup_compressed_vs_plain": round(comp / vp, 3) if comp else None}
+    if not args.no_ablation:
+        out["ablation"] = ablation(P, x0, v0, box, args.ablation_steps)
+    if not args.no_strides:
+        out["stride_sweep"] = stride_sweep(P, cfg, params, x0, v0, box, args.stride_steps)
     if not args.no_serve:
         out["serving"] = serving(P, model, args.serve_requests)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out))
+
+
+def ablation(P, x0, v0, box, steps):
+    """The optimization ladder, FP32, same MD protocol: the plain network;
+    the tabulated G materialised; fused per neighbor over all sel rows;
+    fused per neighbor over the real neighbors only; fused per table-interval
+    run (the default).  At sel = 192 (the copper model) and sel = 512 (the
+    padding regime of the paper's ablation), with weights drawn for each."""
+    import gc
+    import torch
+    import synth
+    rungs = (("plain", P.PLAIN), ("tabulated_unfused", P.TAB_UNFUSED), ("fused_padded", P.FUSED_PADDED),
+             ("fused", P.FUSED), ("fused_interval_runs", P.COMPRESSED))
+    out = {}
+    N = len(x0)
+    for sel in (192, 512):
+        cfg = synth.copper_model_config(sel=sel)
+        m = P.Model(cfg, synth.model_params(cfg)).tabulate(0.7, 0.01, 1.5, 0.1)
+        rows = {}
+        for name, mode in rungs:
+            r = run_nve(P, m, x0, v0, box, steps, 1, P.FP32, mode=mode)
+            emb = sum(v[0] / steps for k, v in r["kernels"].items()
+                      if k.startswith(("emb", "plain", "tab_", "dT", "force_gather")))
+            rows[name] = {"atom_steps_per_s": round(N * steps / (r["ms"] * 1e-3), 1),
+                          "ms_per_step": round(r["ms"] / steps, 4), "embedding_ms_per_step": round(emb, 4)}
+            del r
+            gc.collect()
+            torch.cuda.synchronize()
+        base = rows["plain"]["ms_per_step"]
+        for v in rows.values():
+            v["speedup_vs_plain"] = round(base / v["ms_per_step"], 3)
+        out[f"sel{sel}"] = rows
+        del m
+        gc.collect()
+    return out
+
+
+def stride_sweep(P, cfg, params, x0, v0, box, steps):
+    """The table stride h of the fine range [0, 0.7) (tail 0.1 to 1.5): table
+    size, segments per atom, FP32 MD speed, and the error of one evaluation
+    of the start configuration against the untabulated network (the plain
+    FP64 path of the same library, which the tests hold to the oracle at
+    1e-10)."""
+    import torch
+    x = torch.tensor(x0, dtype=torch.float64, device="cuda")
+    ref_model = P.Model(cfg, params).tabulate(0.7, 0.01, 1.5, 0.1)
+    nl = P.NeighborList(ref_model, x, box, skin=2.0)
+    ref = P.compute(ref_model, nl, x, mode=P.PLAIN, precision=P.FP64)
+    Fr = ref["F"]
+    Frms = float(torch.sqrt(torch.mean(Fr * Fr)))
+    N = x.shape[0]
+    rows = []
+    for h in (0.1, 0.01, 0.001):
+        m = P.Model(cfg, params).tabulate(0.7, h, 1.5, 0.1)
+        nint = int(round(0.7 / h)) + 8
+        row = {"stride": h, "intervals": nint, "table_bytes_fp32": nint * 128 * 8 * 4,
+               "table_bytes_fp64": nint * 128 * 6 * 8}
+        for prec, tag in ((P.FP64, "fp64"), (P.FP32, "fp32")):
+            o = P.compute(m, nl, x, precision=prec)
+            dE = abs(float(o["E"][0] - ref["E"][0])) / N
+            eF = float(torch.sqrt(torch.mean((o["F"] - Fr) ** 2)))
+            row[f"{tag}_dE_per_atom"] = dE
+            row[f"{tag}_rmse_F"] = eF
+            row[f"{tag}_rmse_F_rel"] = eF / Frms
+        d = P.descriptor(m, nl, x, precision=P.FP32)
+        row["mean_segments"] = float(d["nseg"].float().mean())
+        r = run_nve(P, m, x0, v0, box, steps, 2, P.FP32)
+        row["fp32_atom_steps_per_s"] = round(N * steps / (r["ms"] * 1e-3), 1)
+        row["fp32_ms_per_step"] = round(r["ms"] / steps, 4)
+        row["kernels_ms"] = {k: round(v[0] / max(v[1], 1), 4) for k, v in r["kernels"].items()
+                             if k in ("emb_fwd", "emb_bwd")}
+        rows.append(row)
+        del m
+    return rows
 
 
 def serving(P, model, nreq):

@@ -53,15 +53,21 @@ typedef enum {
     DP_MIXED_BF16 = 2   /* as FP32, fitting-net GEMMs on BF16 MFMA, FP32 accumulate */
 } dp_precision;
 
+/* How the embedding stage is evaluated.  All modes compute the same model;
+ * modes 1-4 are the rungs of the paper's step-by-step evaluation of its
+ * optimizations (Sec. 3, and the ablation in its evaluation section). */
 typedef enum {
-    DP_COMPRESSED = 0,  /* tabulated embedding fused with the contraction (Sec. 3) */
-    DP_PLAIN = 1        /* embedding net evaluated layer by layer, padded to sel   */
+    DP_COMPRESSED = 0,    /* tabulated, fused, per table-interval run of neighbors (default) */
+    DP_PLAIN = 1,         /* embedding net evaluated layer by layer, padded to sel            */
+    DP_TAB_UNFUSED = 2,   /* G and G' of every padded row from the table, materialised         */
+    DP_FUSED_PADDED = 3,  /* tabulated and fused per neighbor, padded rows included (Sec. 3.4.1) */
+    DP_FUSED = 4          /* as 3 without the padded rows (redundancy removal, Sec. 3.4.2)    */
 } dp_mode;
 
 /* Model hyper-parameters (Sec. 2.1 and the physical-systems section).
  *   ntypes      must be 1 (one element, copper);
  *   rcut        cut-off R_c (A); rcut_smth: start of the gate w(r) (A);
- *   sel         N_m: neighbors kept per atom (the nearest sel within rcut);
+ *   sel         N_m: neighbors kept per atom (the nearest sel within rcut), 1..512;
  *   emb         embedding widths d1, 2 d1, 4 d1 (M = emb[2]); emb[2] must be 128;
  *   m_lt        M<, columns of G kept in G< (Eq. 2); must be 16;
  *   fit         fitting-net hidden widths (each at most 256);
@@ -136,7 +142,7 @@ dp_status dp_nlist_destroy(dp_nlist *nlist);
  *   atom_energy_d[natoms]  E_i
  * Passing force_d == NULL and virial_d == NULL runs the forward pass only.
  * mode DP_PLAIN evaluates the embedding net layer by layer over sel padded
- * rows (the untabulated baseline); DP_COMPRESSED needs dp_tabulate first. */
+ * rows (the untabulated baseline); every other mode needs dp_tabulate first. */
 dp_status dp_compute(dp_model *model, dp_nlist *nlist, int natoms, const double *coords_d,
                      const int *types_d, const double *box_h, int mode, int precision,
                      double *energy_d, double *force_d, double *virial_d,

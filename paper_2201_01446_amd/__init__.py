@@ -6,5 +6,5 @@ of include/dp.h).  This package is the thin Python side: `Model`,
 `autograd`, and the serving loop in `serve`.  PyTorch provides device memory
 and streams only.
 """
-from .api import (COMPRESSED, FP32, FP64, MIXED_BF16, PLAIN, DPError, Model, NeighborList,  # noqa: F401
-                  compute, descriptor, nve_run)
+from .api import (COMPRESSED, FP32, FP64, FUSED, FUSED_PADDED, MIXED_BF16, PLAIN, TAB_UNFUSED, DPError,  # noqa: F401
+                  Model, NeighborList, compute, descriptor, nve_run)

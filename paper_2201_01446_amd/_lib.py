@@ -15,7 +15,7 @@ DP_OK = 0
 STATUS = {0: "DP_OK", -1: "DP_ERR_ARG", -2: "DP_ERR_HIP", -3: "DP_ERR_OOM", -4: "DP_ERR_CAPACITY",
           -5: "DP_ERR_UNSUPPORTED", -6: "DP_ERR_STATE", -7: "DP_ERR_NONFINITE"}
 FP64, FP32, MIXED_BF16 = 0, 1, 2
-COMPRESSED, PLAIN = 0, 1
+COMPRESSED, PLAIN, TAB_UNFUSED, FUSED_PADDED, FUSED = 0, 1, 2, 3, 4
 
 
 class DPError(RuntimeError):

@@ -8,7 +8,8 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import COMPRESSED, FP32, FP64, MIXED_BF16, PLAIN, DPError, ModelConfig, check, lib  # noqa: F401
+from ._lib import (COMPRESSED, FP32, FP64, FUSED, FUSED_PADDED, MIXED_BF16, PLAIN, TAB_UNFUSED, DPError,  # noqa: F401
+                   ModelConfig, check, lib)
 
 
 def _stream():

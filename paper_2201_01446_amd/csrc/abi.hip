@@ -256,9 +256,9 @@ dp_status check_compute_args(const dp_model *m, const dp_nlist *nl, int natoms, 
 {
     if (!m || !nl || !x) return fail(DP_ERR_ARG, "NULL model, list or coordinates");
     if (natoms != nl->natoms) return fail(DP_ERR_ARG, "natoms differs from the list's");
-    if (mode != DP_COMPRESSED && mode != DP_PLAIN) return fail(DP_ERR_ARG, "unknown mode");
+    if (mode < DP_COMPRESSED || mode > DP_FUSED) return fail(DP_ERR_ARG, "unknown mode");
     if (precision < DP_FP64 || precision > DP_MIXED_BF16) return fail(DP_ERR_ARG, "unknown precision");
-    if (mode == DP_COMPRESSED && !m->tab64) return fail(DP_ERR_STATE, "dp_tabulate has not run");
+    if (mode != DP_PLAIN && !m->tab64) return fail(DP_ERR_STATE, "dp_tabulate has not run");
     return DP_OK;
 }
 
@@ -276,7 +276,8 @@ dp_status dp_model_create(const dp_model_config *cfg, const double *params_h, si
     if (c.ntypes != 1) return fail(DP_ERR_UNSUPPORTED, "ntypes must be 1");
     if (!(c.rcut > 0) || !(c.rcut_smth >= 0) || !(c.rcut_smth < c.rcut))
         return fail(DP_ERR_ARG, "need 0 <= rcut_smth < rcut");
-    if (c.sel < 1 || c.sel > 256) return fail(DP_ERR_UNSUPPORTED, "sel must be in [1, 256]");
+    // the kernels keep up to sel neighbors per atom in LDS (64 KB per block)
+    if (c.sel < 1 || c.sel > 512) return fail(DP_ERR_UNSUPPORTED, "sel must be in [1, 512]");
     if (c.emb[2] != kM || c.emb[1] * 2 != c.emb[2] || c.emb[0] * 2 != c.emb[1])
         return fail(DP_ERR_UNSUPPORTED, "embedding widths must be 32, 64, 128");
     if (c.m_lt != kMlt) return fail(DP_ERR_UNSUPPORTED, "M< must be 16");
@@ -490,7 +491,8 @@ static dp_status compute_common(dp_model *m, dp_nlist *nl, int natoms, const dou
     a.phase = phase;
     // any forward overwrites the kept activations
     nl->fwd_token = phase == 1 ? precision + 1 + 8 * mode : (phase == 2 ? nl->fwd_token : 0);
-    return mode == DP_COMPRESSED ? run_compressed(a, st) : run_plain(a, st);
+    a.mode = mode;
+    return (mode == DP_PLAIN || mode == DP_TAB_UNFUSED) ? run_plain(a, st) : run_compressed(a, st);
 }
 
 dp_status dp_compute(dp_model *m, dp_nlist *nl, int natoms, const double *coords_d, const int *types_d,

@@ -105,9 +105,14 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
     bool fwd = a.phase != 2, bwd = a.need_forces && a.phase != 1;
     if (fwd) {
         if (PLAIN) {
-            if ((s = plain_forward<TR, TA>(m, a.nl, n, a.x, w.T, w.D, a.nnei_out, st)) != DP_OK) return s;
-        } else {
+            bool tab = a.mode == DP_TAB_UNFUSED;
+            if ((s = plain_forward<TR, TA>(m, a.nl, n, a.x, w.T, w.D, a.nnei_out, st, tab)) != DP_OK) return s;
+        } else if (a.mode == DP_COMPRESSED) {
             DP_TIMED("emb_fwd", st, launch_emb_fwd(m, a.nl, n, a.x, a.precision, w.T, w.D, w.rec, w.rcnt, a.nnei_out, a.nseg_out, st));
+            if ((s = step_check("emb_fwd", st)) != DP_OK) return s;
+        } else {
+            bool pad = a.mode == DP_FUSED_PADDED;
+            DP_TIMED("emb_fwd_pn", st, launch_emb_fwd_pn(m, a.nl, n, a.x, a.precision, w.T, w.D, w.rec, w.rcnt, pad, a.nnei_out, st));
             if ((s = step_check("emb_fwd", st)) != DP_OK) return s;
         }
         if (a.T_out) launch_to_double<TR>((long)n * 4 * kM, (const TR *)w.T, a.T_out, st);
@@ -133,11 +138,17 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
         if (PLAIN) {
             DP_TIMED("dT", st, launch_dT<TR>(n, (const TR *)w.dDr, (const TR *)w.T, (TR *)w.dT, st));
             if ((s = step_check("fitting_backward", st)) != DP_OK) return s;
-            if ((s = plain_backward<TR>(m, a.nl, n, w.dT, a.force, w.w_atom, st)) != DP_OK) return s;
+            bool tab = a.mode == DP_TAB_UNFUSED;
+            if ((s = plain_backward<TR>(m, a.nl, n, w.dT, a.force, w.w_atom, st, tab)) != DP_OK) return s;
         } else {
             if ((s = step_check("fitting_backward", st)) != DP_OK) return s;
             // dE/dT is formed inside the fused backward from dE/dD and T
-            DP_TIMED("emb_bwd", st, launch_emb_bwd(m, a.nl, n, a.x, a.precision, w.T, w.dDr, w.rec, w.rcnt, a.force, w.w_atom, st));
+            if (a.mode == DP_COMPRESSED) {
+                DP_TIMED("emb_bwd", st, launch_emb_bwd(m, a.nl, n, a.x, a.precision, w.T, w.dDr, w.rec, w.rcnt, a.force, w.w_atom, st));
+            } else {
+                bool pad = a.mode == DP_FUSED_PADDED;
+                DP_TIMED("emb_bwd_pn", st, launch_emb_bwd_pn(m, a.nl, n, a.x, a.precision, w.T, w.dDr, w.rec, w.rcnt, pad, a.force, w.w_atom, st));
+            }
             DP_TIMED("force_gather", st, launch_force_gather(a.nl, n, a.precision, a.force, st));
             if ((s = step_check("emb_bwd", st)) != DP_OK) return s;
         }

@@ -161,6 +161,15 @@ inline long round_up(long a, long b) { return (a + b - 1) / b * b; }
 // padded to a multiple of 8 (xcd_grid) and items past the real count exit.
 // Only locality depends on the dealing order, never correctness.
 constexpr int kXcd = 8;
+
+// Waves (atoms) per block for a kernel that needs per_wave bytes of LDS per
+// wave: 4 when they fit 64 KB, else 2, else 1 (0: too large).
+inline int lds_wpb(size_t per_wave)
+{
+    for (int w = 4; w >= 1; w >>= 1)
+        if ((size_t)w * per_wave <= 65536) return w;
+    return 0;
+}
 inline int xcd_grid(long nblocks) { return (int)round_up(nblocks, kXcd); }
 __device__ inline int xcd_item(int b, int grid) { return (b % kXcd) * (grid / kXcd) + b / kXcd; }
 
@@ -225,6 +234,12 @@ void launch_to_double(long n, const T *a, double *b, hipStream_t st);
 // GEMM operand matrix (n rows, ncols logical columns) to FP64 (hi + lo for BF16)
 template <typename T>
 void launch_op_to_double(int n, int ncols, const T *a, double *b, hipStream_t st);
+// The per-neighbor rungs of the ablation (padded: rows up to sel included).
+void launch_emb_fwd_pn(const dp_model *m, const dp_nlist *nl, int n, const double *x, int precision, void *T,
+                       void *D, void *rec, int *rcnt, bool padded, int *nnei, hipStream_t st);
+void launch_emb_bwd_pn(const dp_model *m, const dp_nlist *nl, int n, const double *x, int precision, const void *T,
+                       const void *dD, const void *rec, const int *rcnt, bool padded, double *force, double *w_atom,
+                       hipStream_t st);
 // rec/rcnt: the forward's compacted neighbor records (sel slots per atom) and
 // their counts, written by launch_emb_fwd and read by launch_emb_bwd
 void launch_emb_fwd(const dp_model *m, const dp_nlist *nl, int n, const double *x, int precision, void *T,
@@ -245,15 +260,17 @@ struct ComputeArgs {
     double *T_out, *D_out;
     bool need_forces;
     int phase;   // 0: whole step; 1: forward only, activations kept; 2: backward from kept activations
+    int mode = 0;                  // dp_mode
     int nseg = 0;                  // >0: E and W per segment (request) of a batch instead of totals
     const int *seg_off = nullptr;  // device [nseg + 1] atom offsets of the segments
 };
+// tabulated: the tabulated-but-unfused rung (G materialised from the table)
 template <typename real, typename TD>
 dp_status plain_forward(const dp_model *m, dp_nlist *nl, int n, const double *x, void *T, void *D, int *nnei,
-                        hipStream_t st);
+                        hipStream_t st, bool tabulated);
 template <typename real>
 dp_status plain_backward(const dp_model *m, dp_nlist *nl, int n, const void *dT, double *force, double *w_atom,
-                         hipStream_t st);
+                         hipStream_t st, bool tabulated);
 dp_status ensure_ws(dp_nlist *nl, int precision, int sel);
 // Reverse slots of the candidate lists of atoms [off, off + n) (after a build).
 void launch_reverse(dp_nlist *nl, int off, int n, hipStream_t st);

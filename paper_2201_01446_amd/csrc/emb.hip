@@ -493,7 +493,7 @@ static void launch_fwd_t(const dp_model *m, const dp_nlist *nl, int n, const dou
     A.rcnt = rcnt;
     A.pg = nl->pg;
     const real *tab = std::is_same<real, double>::value ? (const real *)m->tab64 : (const real *)m->tab32;
-    int wpb = 4;
+    int wpb = lds_wpb(fwd_lds_bytes<real>(A.sel));
     size_t lds = (size_t)wpb * fwd_lds_bytes<real>(A.sel);
     hipLaunchKernelGGL((k_emb_fwd<real, TD>), dim3(xcd_grid(div_up(n, wpb))), dim3(64 * wpb), lds, st, n, A, tab,
                        (real)m->cfg.desc_scale, (real *)T, (TD *)D, nnei, nseg);
@@ -509,7 +509,7 @@ static void launch_bwd_t(const dp_model *m, const dp_nlist *nl, int n, const dou
     A.rcnt = const_cast<int *>(rcnt);
     A.pg = nl->pg;
     const real *tab = std::is_same<real, double>::value ? (const real *)m->tab64 : (const real *)m->tab32;
-    int wpb = 4;
+    int wpb = lds_wpb(bwd_lds_bytes<real>(A.sel));
     size_t lds = (size_t)wpb * bwd_lds_bytes<real>(A.sel);
     hipLaunchKernelGGL((k_emb_bwd<real, CPL>), dim3(xcd_grid(div_up(n, wpb))), dim3(64 * wpb), lds, st, n, A, tab,
                        (real)m->cfg.desc_scale, (const real *)T, (const real *)dD, force, w_atom);

@@ -40,8 +40,9 @@ struct EnvArgs {
 // What a kernel keeps per neighbor in its LDS slice.
 enum EnvMode {
     ENV_FWD = 0,    // R_j, t_j, interval
-    ENV_BWD = 1,    // r_ij, t_j, interval, neighbor index j (R_j is recomputed from r_ij)
-    ENV_PLAIN = 2   // R_j, r_ij, (t, ds/dr, 1/r, s), interval, j for the untabulated path
+    ENV_BWD = 1,    // r_ij, t_j, interval, candidate slot (R_j is recomputed from r_ij)
+    ENV_PLAIN = 2,  // R_j, r_ij, (t, ds/dr, 1/r, s), interval, j for the untabulated path
+    ENV_BWDR = 3    // r_ij, R_j, t_j, interval, candidate slot (per-neighbor backward)
 };
 
 // Per-wave LDS slice (arrays of sel entries; V4 arrays first for alignment).
@@ -93,6 +94,32 @@ __device__ inline void env_geom(const EnvArgs &A, const V4<real> &d, real &rinv,
 
 __device__ inline int s8(int v, int sh) { return (int)(signed char)((v >> sh) & 0xFF); }
 
+// Table interval of s (left-closed) and the offset t from its left node;
+// returns 1 when s lies past the table end: then s is clamped there (G is
+// constant, G' = 0) and bit 30 of th tells the backward to drop G'.
+template <typename real>
+__device__ inline int table_interval(const EnvArgs &A, real s, int &th, real &t)
+{
+    if (s < (real)A.s_max) {
+        int q = (int)floor(s / (real)A.h);
+        q = q > 0 ? q : 0;
+        th = q < A.n_fine - 1 ? q : A.n_fine - 1;
+        t = s - (real)th * (real)A.h;
+        return 0;
+    }
+    if (A.n_tail > 0 && s < (real)A.tail_max) {
+        int q = (int)floor((s - (real)A.s_max) / (real)A.h_tail);
+        q = q > 0 ? q : 0;
+        q = q < A.n_tail - 1 ? q : A.n_tail - 1;
+        th = A.n_fine + q;
+        t = s - ((real)A.s_max + (real)q * (real)A.h_tail);
+        return 0;
+    }
+    th = (A.n_fine + A.n_tail - 1) | kOobBit;
+    t = (real)(A.n_tail > 0 ? A.h_tail : A.h);
+    return 1;
+}
+
 // Record of one compacted neighbor: r_ij and its candidate slot c (< 2^24,
 // exact in either precision's mantissa).
 __device__ inline int record_slot(float w) { return __builtin_bit_cast(int, w); }
@@ -140,31 +167,12 @@ __device__ int finish_env(const EnvArgs &A, NbrLDS<real> L, int nn, int lane)
 {
     int oob = 0;
     for (int k = lane; k < nn; k += 64) {
-        V4<real> d = MODE == ENV_BWD ? L.Dv[k] : L.R[k];
+        V4<real> d = (MODE == ENV_BWD || MODE == ENV_BWDR) ? L.Dv[k] : L.R[k];
         real rinv, s, sp;
         env_geom<real>(A, d, rinv, s, sp);
-        // table interval of s (left-closed) and offset from its left node
         int th = 0;
         real t = 0;
-        if (!TAB) {
-        } else if (s < (real)A.s_max) {
-            int q = (int)floor(s / (real)A.h);
-            q = q > 0 ? q : 0;
-            th = q < A.n_fine - 1 ? q : A.n_fine - 1;
-            t = s - (real)th * (real)A.h;
-        } else if (A.n_tail > 0 && s < (real)A.tail_max) {
-            int q = (int)floor((s - (real)A.s_max) / (real)A.h_tail);
-            q = q > 0 ? q : 0;
-            q = q < A.n_tail - 1 ? q : A.n_tail - 1;
-            th = A.n_fine + q;
-            t = s - ((real)A.s_max + (real)q * (real)A.h_tail);
-        } else {
-            // clamped to the table end: G is constant there, so G' = 0
-            // (flag bit 30 on the interval tells the backward to drop G')
-            th = (A.n_fine + A.n_tail - 1) | kOobBit;
-            t = (real)(A.n_tail > 0 ? A.h_tail : A.h);
-            oob++;
-        }
+        if (TAB) oob += table_interval<real>(A, s, th, t);
         if (MODE != ENV_BWD) L.R[k] = V4<real>{s, s * d.x * rinv, s * d.y * rinv, s * d.z * rinv};
         L.t[k] = t;
         L.th[k] = th;
@@ -257,7 +265,7 @@ __device__ int build_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane, int 
 
 // The backward's neighbors of atom i: read back the forward's records (no
 // scan of the skin list), then the same per-neighbor quantities.
-template <typename real>
+template <typename real, int MODE = ENV_BWD>
 __device__ int load_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane)
 {
     int nn = A.rcnt[i];
@@ -270,7 +278,7 @@ __device__ int load_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    finish_env<real, ENV_BWD, true>(A, L, nn, lane);
+    finish_env<real, MODE, true>(A, L, nn, lane);
     return nn;
 }
 
@@ -291,7 +299,7 @@ __device__ inline void record_flags(const EnvArgs &A, int lane, int n_in, int oo
 template <typename real>
 constexpr int nbr_lds_bytes(int sel, int mode)
 {
-    int v4 = mode == ENV_PLAIN ? 3 : 1;
+    int v4 = mode == ENV_PLAIN ? 3 : (mode == ENV_BWDR ? 2 : 1);
     int ints = mode == ENV_FWD ? 1 : 2;
     int b = sel * (v4 * (int)sizeof(V4<real>) + (int)sizeof(real) + ints * 4);
     constexpr int al = (int)sizeof(V4<real>);

@@ -154,15 +154,77 @@ __global__ void k_plain_dG(long rows, int sel, real sigma, const V4<real> *__res
     h1dGf[row * 64 + c] = g0 + g1;
 }
 
-// Per atom (block), per row (thread): dE/ds through G (dz0 . W0) and through
-// R (dR . u), then g_ij = dE_i/dr_ij; forces by atomics, virial per atom.
+// Tabulated but unfused (the intermediate rung between the plain and the
+// fused paths): G and G' = dG/ds of every row, padded rows included, written
+// to memory from the table (Sec. 3.2), one thread per (row, column).
+template <typename real>
+__device__ inline void tab_coef(const real *tab, int th, int c, real (&a)[6])
+{
+    if (sizeof(real) == 4) {
+        const real *p = tab + ((long)th * kM + c) * 8;
+        for (int e = 0; e < 6; e++) a[e] = p[e];
+    } else {
+        const real *p = tab + ((long)th * kM + c) * 6;
+        for (int e = 0; e < 6; e++) a[e] = p[e];
+    }
+}
+
+template <typename real>
+__global__ void k_tab_eval(long rows, EnvArgs A, const real *__restrict__ tab, const real *__restrict__ s,
+                           real *__restrict__ G, real *__restrict__ Gp)
+{
+    long id = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (id >= rows * kM) return;
+    long row = id >> 7;
+    int c = (int)(id & (kM - 1));
+    int th;
+    real t;
+    int oob = table_interval<real>(A, s[row], th, t);
+    real a[6];
+    tab_coef<real>(tab, th & ~kOobBit, c, a);
+    real f = a[5], fp = a[5];
+    for (int e = 4; e >= 1; e--) {
+        f = fma(f, t, a[e]);
+        fp = fma(fp, t, f);
+    }
+    f = fma(f, t, a[0]);
+    G[id] = f;
+    Gp[id] = oob ? (real)0 : fp;
+}
+
+// dE/ds through the tabulated G: sum_c (sig sum_k R_k dT[k][c]) G'[c]; one
+// wave per row, lanes over columns.
+template <typename real>
+__global__ void __launch_bounds__(256) k_tab_dsG(long rows, int sel, real sigma, const V4<real> *__restrict__ R,
+                                                 const real *__restrict__ dT, const real *__restrict__ Gp,
+                                                 real *__restrict__ dsG)
+{
+    long row = blockIdx.x * 4L + (threadIdx.x >> 6);
+    int lane = threadIdx.x & 63;
+    if (row >= rows) return;
+    long atom = row / sel;
+    V4<real> r = R[row];
+    const real *d = dT + atom * 4 * kM;
+    real acc = 0;
+    for (int c = lane; c < kM; c += 64) {
+        real g = d[c] * r.x + d[kM + c] * r.y + d[2 * kM + c] * r.z + d[3 * kM + c] * r.w;
+        acc = fma(sigma * g, Gp[row * kM + c], acc);
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) dsG[row] = acc;
+}
+
+// Per atom (block), per row (thread): dE/ds through G (dz0 . W0, or the
+// row's dsG in the tabulated rung) and through R (dR . u), then
+// g_ij = dE_i/dr_ij; forces by atomics, virial per atom.
 template <typename real>
 __global__ void __launch_bounds__(256) k_plain_force(int natoms, int sel, real sigma,
                                                      const V4<real> *__restrict__ R,
                                                      const V4<real> *__restrict__ P,
                                                      const V4<real> *__restrict__ Dv, const int *__restrict__ jrow,
                                                      const real *__restrict__ G, const real *__restrict__ dz0,
-                                                     const real *__restrict__ W0, const real *__restrict__ dT,
+                                                     const real *__restrict__ W0, const real *__restrict__ dsG_row,
+                                                     const real *__restrict__ dT,
                                                      double *__restrict__ force, double *__restrict__ w_atom)
 {
     __shared__ real dTs[4 * kM];
@@ -176,7 +238,9 @@ __global__ void __launch_bounds__(256) k_plain_force(int natoms, int sel, real s
         int j = jrow[row];
         if (j >= 0) {
             real dsG = 0;
-            for (int a = 0; a < 32; a++) dsG = fma(dz0[row * 32 + a], W0[a], dsG);
+            if (dsG_row) dsG = dsG_row[row];
+            else
+                for (int a = 0; a < 32; a++) dsG = fma(dz0[row * 32 + a], W0[a], dsG);
             real dR0 = 0, dR1 = 0, dR2 = 0, dR3 = 0;
             const real *g = G + row * kM;
             for (int e = 0; e < kM; e++) {
@@ -297,9 +361,10 @@ dp_status plain_ensure(dp_nlist *nl, long rows)
 }
 
 // Forward of the embedding stage: T (real) and D (TD) for every atom.
+// tabulated: G from the table (materialised) instead of the network.
 template <typename real, typename TD>
 dp_status plain_forward(const dp_model *m, dp_nlist *nl, int n, const double *x, void *T, void *D, int *nnei,
-                        hipStream_t st)
+                        hipStream_t st, bool tabulated)
 {
     int sel = m->cfg.sel;
     long rows = (long)n * sel, rows_p = round_up(rows, kRowPad);
@@ -308,19 +373,27 @@ dp_status plain_forward(const dp_model *m, dp_nlist *nl, int n, const double *x,
     PlainWS<real> w = plain_carve<real>(nl->ws_plain, rows_p);
     EmbW<real> ew = emb_weights<real>(m);
     EnvArgs A = make_env_args(m, nl, x);
-    int wpb = 4;
+    int wpb = lds_wpb(nbr_lds_bytes<real>(A.sel, ENV_PLAIN));
     size_t lds = (size_t)wpb * nbr_lds_bytes<real>(A.sel, ENV_PLAIN);
     DP_TIMED("plain_env", st,
              hipLaunchKernelGGL((k_plain_env<real>), dim3(div_up(n, wpb)), dim3(64 * wpb), lds, st, n, A, w.s, w.R,
                                 w.P, w.Dv, w.j, nnei));
-    DP_TIMED("plain_l0", st,
-             hipLaunchKernelGGL((k_plain_l0<real>), dim3(div_up(rows * 32, 256)), dim3(256), 0, st, rows, w.s, ew.W0,
-                                ew.b0, w.h0));
-    Epi e{};
-    e = Epi{ew.b1, w.h0, nullptr, nullptr, w.h1, nullptr, w.t1, 32, 0};
-    DP_TIMED("plain_gemm", st, launch_gemm<real, real>(EPI_EMB, (int)rows_p, 64, 32, w.h0, ew.W1t, e, st));
-    e = Epi{ew.b2, w.h1, nullptr, nullptr, w.G, nullptr, w.t2, 64, 0};
-    DP_TIMED("plain_gemm", st, launch_gemm<real, real>(EPI_EMB, (int)rows_p, kM, 64, w.h1, ew.W2t, e, st));
+    if (tabulated) {
+        // G and G' (in t2) of every row from the table
+        const real *tab = std::is_same<real, double>::value ? (const real *)m->tab64 : (const real *)m->tab32;
+        DP_TIMED("tab_eval", st,
+                 hipLaunchKernelGGL((k_tab_eval<real>), dim3(div_up(rows * kM, 256)), dim3(256), 0, st, rows, A, tab,
+                                    w.s, w.G, w.t2));
+    } else {
+        DP_TIMED("plain_l0", st,
+                 hipLaunchKernelGGL((k_plain_l0<real>), dim3(div_up(rows * 32, 256)), dim3(256), 0, st, rows, w.s,
+                                    ew.W0, ew.b0, w.h0));
+        Epi e{};
+        e = Epi{ew.b1, w.h0, nullptr, nullptr, w.h1, nullptr, w.t1, 32, 0};
+        DP_TIMED("plain_gemm", st, launch_gemm<real, real>(EPI_EMB, (int)rows_p, 64, 32, w.h0, ew.W1t, e, st));
+        e = Epi{ew.b2, w.h1, nullptr, nullptr, w.G, nullptr, w.t2, 64, 0};
+        DP_TIMED("plain_gemm", st, launch_gemm<real, real>(EPI_EMB, (int)rows_p, kM, 64, w.h1, ew.W2t, e, st));
+    }
     DP_TIMED("plain_contract", st,
              hipLaunchKernelGGL((k_plain_contract<real, TD>), dim3(div_up(n, 4)), dim3(256), 0, st, n, sel,
                                 (real)m->cfg.desc_scale, w.R, w.G, (real *)T, (TD *)D));
@@ -329,13 +402,25 @@ dp_status plain_forward(const dp_model *m, dp_nlist *nl, int n, const double *x,
 
 template <typename real>
 dp_status plain_backward(const dp_model *m, dp_nlist *nl, int n, const void *dT, double *force, double *w_atom,
-                         hipStream_t st)
+                         hipStream_t st, bool tabulated)
 {
     int sel = m->cfg.sel;
     long rows = (long)n * sel, rows_p = round_up(rows, kRowPad);
     PlainWS<real> w = plain_carve<real>(nl->ws_plain, rows_p);
     EmbW<real> ew = emb_weights<real>(m);
     real sig = (real)m->cfg.desc_scale;
+    if (tabulated) {
+        // dE/ds of every row through the tabulated G' (into s), then the forces
+        DP_TIMED("tab_dsG", st,
+                 hipLaunchKernelGGL((k_tab_dsG<real>), dim3(div_up(rows, 4)), dim3(256), 0, st, rows, sel, sig, w.R,
+                                    (const real *)dT, w.t2, w.s));
+        launch_fill_zero(force, 3L * n, st);
+        DP_TIMED("plain_force", st,
+                 hipLaunchKernelGGL((k_plain_force<real>), dim3(n), dim3(256), 0, st, n, sel, sig, w.R, w.P, w.Dv,
+                                    w.j, w.G, (const real *)nullptr, ew.W0, (const real *)w.s, (const real *)dT, force,
+                                    w_atom));
+        return step_check("tab_backward", st);
+    }
     DP_TIMED("plain_dG", st,
              hipLaunchKernelGGL((k_plain_dG<real>), dim3(div_up(rows * 64, 256)), dim3(256), 0, st, rows, sel, sig, w.R,
                                 (const real *)dT, w.t2, w.h1));
@@ -349,19 +434,19 @@ dp_status plain_backward(const dp_model *m, dp_nlist *nl, int n, const void *dT,
     launch_fill_zero(force, 3L * n, st);
     DP_TIMED("plain_force", st,
              hipLaunchKernelGGL((k_plain_force<real>), dim3(n), dim3(256), 0, st, n, sel, sig, w.R, w.P, w.Dv, w.j,
-                                w.G, w.h0, ew.W0, (const real *)dT, force, w_atom));
+                                w.G, w.h0, ew.W0, (const real *)nullptr, (const real *)dT, force, w_atom));
     return step_check("plain_backward", st);
 }
 
 template dp_status plain_forward<double, double>(const dp_model *, dp_nlist *, int, const double *, void *, void *,
-                                                 int *, hipStream_t);
+                                                 int *, hipStream_t, bool);
 template dp_status plain_forward<float, float>(const dp_model *, dp_nlist *, int, const double *, void *, void *,
-                                               int *, hipStream_t);
+                                               int *, hipStream_t, bool);
 template dp_status plain_forward<float, __bf16>(const dp_model *, dp_nlist *, int, const double *, void *, void *,
-                                                int *, hipStream_t);
+                                                int *, hipStream_t, bool);
 template dp_status plain_backward<double>(const dp_model *, dp_nlist *, int, const void *, double *, double *,
-                                          hipStream_t);
+                                          hipStream_t, bool);
 template dp_status plain_backward<float>(const dp_model *, dp_nlist *, int, const void *, double *, double *,
-                                         hipStream_t);
+                                         hipStream_t, bool);
 
 }  // namespace dp
