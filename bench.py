@@ -73,6 +73,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-strides", action="store_true", help="skip the table-stride sweep")
     ap.add_argument("--no-ablation", action="store_true", help="skip the optimization ladder")
+    ap.add_argument("--no-tanh", action="store_true", help="skip the tabulated-tanh comparison")
     ap.add_argument("--ablation-steps", type=int, default=10)
     ap.add_argument("--stride-steps", type=int, default=20)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -238,6 +239,8 @@ def main():
         out[name] = {"value": round(vp, 1), "ms_per_step": round(res["ms"] / Kp, 4), "steps": Kp,
                      "kernels": {k: round(v[0] / max(v[1], 1), 4) for k, v in res["kernels"].items()},
                      "speedup_compressed_vs_plain": round(comp / vp, 3) if comp else None}
+    if not args.no_tanh:
+        out["tanh_table"] = tanh_compare(P, cfg, params, x0, v0, box, min(K, 50))
     if not args.no_ablation:
         out["ablation"] = ablation(P, x0, v0, box, args.ablation_steps)
     if not args.no_strides:
@@ -247,6 +250,31 @@ def main():
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out))
+
+
+def tanh_compare(P, cfg, params, x0, v0, box, steps):
+    """The fitting net's tanh from the second-order table against the native
+    tanh, FP32: MD speed, fitting-GEMM times, and the change of one
+    evaluation of the start configuration."""
+    import torch
+    N = len(x0)
+    out = {}
+    x = torch.tensor(x0, dtype=torch.float64, device="cuda")
+    res = {}
+    for tab in (False, True):
+        m = P.Model(cfg, params).tabulate(0.7, 0.01, 1.5, 0.1).fitting_tanh(tab)
+        nl = P.NeighborList(m, x, box, skin=2.0)
+        res[tab] = P.compute(m, nl, x, precision=P.FP32)
+        r = run_nve(P, m, x0, v0, box, steps, 2, P.FP32)
+        out["table" if tab else "native"] = {
+            "atom_steps_per_s": round(N * steps / (r["ms"] * 1e-3), 1), "ms_per_step": round(r["ms"] / steps, 4),
+            "fitting_forward_ms": round(sum(v[0] / max(v[1], 1) for k, v in r["kernels"].items()
+                                            if k.startswith("fit_fwd")), 4)}
+        del nl, m
+    a, b = res[False], res[True]
+    out["dE_per_atom"] = abs(float(a["E"][0] - b["E"][0])) / N
+    out["rmse_F_change"] = float(torch.sqrt(torch.mean((a["F"] - b["F"]) ** 2)))
+    return out
 
 
 def ablation(P, x0, v0, box, steps):

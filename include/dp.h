@@ -113,6 +113,15 @@ dp_status dp_model_destroy(dp_model *model);
 dp_status dp_tabulate(dp_model *model, double s_max, double stride, double tail_max,
                       double tail_stride, void *stream);
 
+/* Selects the tanh of the fitting net in the FP32 and mixed modes: 0 the
+ * native tanh (default), 1 a second-order polynomial per interval of width
+ * 1/128 on [0, 8) with the value and slope of tanh at the left node and its
+ * value at the right node, odd extension, 1 beyond 8 (the tabulated tanh of
+ * Sec. 3.5; its largest error, 2.3e-7, is the saturation at 8, and 2.4e-8
+ * inside the range).  FP64 mode always uses tanh.  The table is built on
+ * `stream` at the first call with tabulated = 1.  DP_ERR_ARG on other values. */
+dp_status dp_fitting_tanh(dp_model *model, int tabulated, void *stream);
+
 /* Copies the FP64 table to the host: coef_h[(theta * M + eta) * 6 + xi] is
  * the coefficient of t^xi of column eta on interval theta.  *n_int receives
  * the interval count (coef_h may be NULL to query it).  Synchronises. */

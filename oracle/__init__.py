@@ -41,6 +41,7 @@ class Config(ctypes.Structure):
         ("f3", ctypes.c_int),
         ("desc_scale", ctypes.c_double),
         ("switch_kind", ctypes.c_int),
+        ("tanh_table", ctypes.c_int),
     ]
 
 
@@ -60,6 +61,8 @@ def lib():
         L.orc_param_count.argtypes = [pc]
         L.orc_param_count.restype = l
         L.orc_switch.argtypes = [pc, d, pd, pd]
+        L.orc_tanh_table.argtypes = [d]
+        L.orc_tanh_table.restype = d
         L.orc_embed.argtypes = [pc, pd, d, pd, pd, pd]
         L.orc_hermite.argtypes = [d, d, d, d, d, d, d, pd]
         L.orc_table_intervals.argtypes = [d, d, d, d]
@@ -86,7 +89,8 @@ def _ip(a):
 
 
 def make_config(cfg):
-    """cfg: mapping with rcut, rcut_smth, sel, emb (3), m_lt, fit (3), desc_scale, switch_kind."""
+    """cfg: mapping with rcut, rcut_smth, sel, emb (3), m_lt, fit (3), desc_scale, switch_kind and,
+    optionally, tanh_table (1: the fitting net's tanh from the second-order table)."""
     c = Config()
     c.rcut = cfg["rcut"]
     c.rcut_smth = cfg["rcut_smth"]
@@ -96,6 +100,7 @@ def make_config(cfg):
     c.f1, c.f2, c.f3 = cfg["fit"]
     c.desc_scale = cfg["desc_scale"]
     c.switch_kind = cfg.get("switch_kind", 0)
+    c.tanh_table = cfg.get("tanh_table", 0)
     return c
 
 
@@ -234,3 +239,9 @@ def velocity_verlet(cfg, params, x, v, box, mass, dt, nsteps, table=None):
         v = v + 0.5 * dt * ACC_UNIT * F / mass
         rows.append((out["E"], 0.5 * mass * KE_UNIT * float(np.sum(v * v))))
     return x, v, np.array(rows)
+
+
+def tanh_table(x):
+    """The oracle's tabulated tanh (second order, [0, 8], odd, 1 beyond 8)."""
+    f = lib().orc_tanh_table
+    return np.array([f(float(v)) for v in np.ravel(x)]).reshape(np.shape(x))

@@ -20,6 +20,8 @@
  *   - the tabulation of the embedding net by fifth-order
  *     polynomials matching value, first and second derivative at
  *     both interval nodes                                         (Sec. 3.2)
+ *   - optionally, tanh of the fitting net by a second-order
+ *     polynomial per interval on [0, 8], odd extension, 1 beyond 8 (Sec. 3.5)
  *
  * Readings where the paper is silent (stated once, used everywhere here):
  *   - gate w(r): 1 below r_s, the quintic smoothstep 1-10u^3+15u^4-6u^5 with
@@ -35,7 +37,11 @@
  *     of its interval; interval index min(floor(s/h), n-1) (left-closed);
  *     beyond the last node s is clamped to the table end;
  *   - more than sel neighbors: keep the sel nearest by (r, j, image);
- *   - virial W = - sum_i sum_j r_ij (x) dE_i/dr_ij.
+ *   - virial W = - sum_i sum_j r_ij (x) dE_i/dr_ij;
+ *   - tabulated tanh (tanh_table = 1): intervals of width 1/128 on [0, 8);
+ *     on [x0, x0 + h] the quadratic with the value and slope of tanh at x0
+ *     and its value at x0 + h; its derivative in the backward is taken as
+ *     1 - y^2 of the tabulated y, as for tanh itself.
  *
  * Boxes are orthorhombic (diagonal 3x3, row vectors) or NULL for an open
  * cluster.  Everything is double precision.  Threads: OpenMP over atoms.
@@ -56,6 +62,7 @@ typedef struct {
     int f1, f2, f3;      /* fitting-net hidden widths                     */
     double desc_scale;   /* factor on R^T G                               */
     int switch_kind;     /* 0 quintic smoothstep, 1 cosine                */
+    int tanh_table;      /* 1: tabulated tanh in the fitting net          */
 } orc_config;
 
 /* A tabulated embedding net: n_int intervals, each with M quintics in the
@@ -66,6 +73,27 @@ typedef struct {
     int M;
     const double *coef;
 } orc_table;
+
+/* ------------------------------------------------------- tabulated tanh */
+
+/* tanh of the fitting net by a second-order polynomial per interval of
+ * width 1/128 on [0, 8): value and slope of tanh at the left node, value at
+ * the right node; odd extension; 1 from 8 on (Sec. 3.5 states the order,
+ * the range, the symmetry and the saturation). */
+double orc_tanh_table(double x)
+{
+    const double h = 1.0 / 128.0;
+    double ax = fabs(x);
+    if (ax >= 8.0) return x < 0 ? -1.0 : 1.0;
+    int k = (int)floor(ax / h);
+    double x0 = k * h, t = ax - x0;
+    double a0 = tanh(x0), a1 = 1.0 - a0 * a0;
+    double a2 = (tanh(x0 + h) - a0 - a1 * h) / (h * h);
+    double y = a0 + t * (a1 + t * a2);
+    return x < 0 ? -y : y;
+}
+
+static double act(const orc_config *c, double z) { return c->tanh_table ? orc_tanh_table(z) : tanh(z); }
 
 /* ---------------------------------------------------------------- params */
 
@@ -460,19 +488,19 @@ static int atom_eval(const orc_config *c, const orc_params *q, const double *par
         double acc = q->c1[o];
         for (int a = 0; a < nD; a++) acc += D[a] * q->V1[(long)a * f1 + o];
         z1[o] = acc;
-        y1[o] = tanh(acc) + (nD == f1 ? D[o] : 0.0);
+        y1[o] = act(c, acc) + (nD == f1 ? D[o] : 0.0);
     }
     for (int o = 0; o < f2; o++) {
         double acc = q->c2[o];
         for (int a = 0; a < f1; a++) acc += y1[a] * q->V2[(long)a * f2 + o];
         z2[o] = acc;
-        y2[o] = tanh(acc) + (f1 == f2 ? y1[o] : 0.0);
+        y2[o] = act(c, acc) + (f1 == f2 ? y1[o] : 0.0);
     }
     for (int o = 0; o < f3; o++) {
         double acc = q->c3[o];
         for (int a = 0; a < f2; a++) acc += y2[a] * q->V3[(long)a * f3 + o];
         z3[o] = acc;
-        y3[o] = tanh(acc) + (f2 == f3 ? y2[o] : 0.0);
+        y3[o] = act(c, acc) + (f2 == f3 ? y2[o] : 0.0);
     }
     double Ei = q->b4[0];
     for (int a = 0; a < f3; a++) Ei += y3[a] * q->w4[a];
@@ -484,19 +512,19 @@ static int atom_eval(const orc_config *c, const orc_params *q, const double *par
         double *dy1 = malloc(sizeof(double) * f1), *dD = malloc(sizeof(double) * nD);
         double *dz = malloc(sizeof(double) * (f1 > f2 ? (f1 > f3 ? f1 : f3) : (f2 > f3 ? f2 : f3)));
         for (int a = 0; a < f3; a++) dy3[a] = q->w4[a];
-        for (int o = 0; o < f3; o++) { double t = tanh(z3[o]); dz[o] = dy3[o] * (1.0 - t * t); }
+        for (int o = 0; o < f3; o++) { double t = act(c, z3[o]); dz[o] = dy3[o] * (1.0 - t * t); }
         for (int a = 0; a < f2; a++) {
             double acc = (f2 == f3) ? dy3[a] : 0.0;
             for (int o = 0; o < f3; o++) acc += q->V3[(long)a * f3 + o] * dz[o];
             dy2[a] = acc;
         }
-        for (int o = 0; o < f2; o++) { double t = tanh(z2[o]); dz[o] = dy2[o] * (1.0 - t * t); }
+        for (int o = 0; o < f2; o++) { double t = act(c, z2[o]); dz[o] = dy2[o] * (1.0 - t * t); }
         for (int a = 0; a < f1; a++) {
             double acc = (f1 == f2) ? dy2[a] : 0.0;
             for (int o = 0; o < f2; o++) acc += q->V2[(long)a * f2 + o] * dz[o];
             dy1[a] = acc;
         }
-        for (int o = 0; o < f1; o++) { double t = tanh(z1[o]); dz[o] = dy1[o] * (1.0 - t * t); }
+        for (int o = 0; o < f1; o++) { double t = act(c, z1[o]); dz[o] = dy1[o] * (1.0 - t * t); }
         for (int a = 0; a < nD; a++) {
             double acc = (nD == f1) ? dy1[a] : 0.0;
             for (int o = 0; o < f1; o++) acc += q->V1[(long)a * f1 + o] * dz[o];

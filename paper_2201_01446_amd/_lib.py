@@ -41,6 +41,7 @@ _SIG = {
     "dp_model_create": [ctypes.POINTER(ModelConfig), _vp, _sz, _pvp],
     "dp_model_destroy": [_vp],
     "dp_tabulate": [_vp, _d, _d, _d, _d, _vp],
+    "dp_fitting_tanh": [_vp, _i, _vp],
     "dp_table_download": [_vp, _vp, _pi],
     "dp_build_nlist": [_vp, _i, _vp, _vp, _vp, _d, _pvp, _vp],
     "dp_nlist_destroy": [_vp],

@@ -62,6 +62,12 @@ class Model:
         self.table_args = (s_max, stride, tail_max, tail_stride)
         return self
 
+    def fitting_tanh(self, tabulated=True):
+        """The fitting net's tanh in the FP32 and mixed modes: the second-order
+        table (True) or the native function (False)."""
+        check(lib.dp_fitting_tanh(self.h, 1 if tabulated else 0, _stream()))
+        return self
+
     def table(self):
         n = ctypes.c_int()
         check(lib.dp_table_download(self.h, None, ctypes.byref(n)))

@@ -370,7 +370,7 @@ dp_status dp_model_create(const dp_model_config *cfg, const double *params_h, si
 dp_status dp_model_destroy(dp_model *m)
 {
     if (!m) return DP_OK;
-    void *p[] = {m->emb_d, m->fitb_d, m->fitb_f, m->tab64, m->tab32, m->nodes, m->embg64, m->embg32};
+    void *p[] = {m->emb_d, m->fitb_d, m->fitb_f, m->tab64, m->tab32, m->nodes, m->embg64, m->embg32, m->tanh_tab};
     for (void *q : p)
         if (q) (void)hipFree(q);
     free_fit(m->w64);
@@ -418,6 +418,19 @@ dp_status dp_tabulate(dp_model *m, double s_max, double stride, double tail_max,
     dp_status s = launch_tabulate(m, (hipStream_t)stream);
     if (s != DP_OK) return s;
     return step_check("tabulate", (hipStream_t)stream);
+}
+
+dp_status dp_fitting_tanh(dp_model *m, int tabulated, void *stream)
+{
+    if (!m || (tabulated != 0 && tabulated != 1)) return fail(DP_ERR_ARG, "bad argument");
+    if (tabulated && !m->tanh_tab) {
+        DP_HIP(hipMalloc(&m->tanh_tab, sizeof(float) * 4 * kTanhN));
+        launch_tanh_table(m->tanh_tab, (hipStream_t)stream);
+        dp_status s = step_check("tanh_table", (hipStream_t)stream);
+        if (s != DP_OK) return s;
+    }
+    m->tanh_on = tabulated;
+    return DP_OK;
 }
 
 dp_status dp_table_download(dp_model *m, double *coef_h, int *n_int)

@@ -117,11 +117,16 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
         }
         if (a.T_out) launch_to_double<TR>((long)n * 4 * kM, (const TR *)w.T, a.T_out, st);
         if (a.D_out) launch_op_to_double<TA>(n, kDdim, (const TA *)w.D, a.D_out, st);
+        // the fitting net's tanh: native, or tabulated in the FP32 and mixed modes when enabled
+        const float *ttab = (a.precision != DP_FP64 && m->tanh_on) ? m->tanh_tab : nullptr;
         e = Epi{c1, nullptr, nullptr, nullptr, w.y1r, w.y1o, nullptr};
+        e.tanh_tab = ttab;
         DP_TIMED("fit_fwd1", st, launch_gemm<TA, TR>(EPI_T1, mr, kFitPad, ks * kDdim, (const TA *)w.D, (const TA *)fw.V1t, e, st));
         e = Epi{c2, w.y1r, nullptr, nullptr, w.y2r, w.y2o, w.t2r};
+        e.tanh_tab = ttab;
         DP_TIMED("fit_fwd2", st, launch_gemm<TA, TR>(EPI_T2, mr, kFitPad, ks * kFitPad, (const TA *)w.y1o, (const TA *)fw.V2t, e, st));
         e = Epi{c3, nullptr, nullptr, nullptr, nullptr, nullptr, w.t3r};
+        e.tanh_tab = ttab;
         DP_TIMED("fit_fwd3", st, launch_gemm<TA, TR>(EPI_T3, mr, kFitPad, ks * kFitPad, (const TA *)w.y2o, (const TA *)fw.V3t, e, st));
     }
     // E_i always; dz3 = w4 (1 - t3^2) when the backward follows

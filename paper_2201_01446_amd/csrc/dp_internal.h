@@ -64,6 +64,10 @@ struct dp_model {
     double *tab64 = nullptr;     // [n_int][M][6]
     float *tab32 = nullptr;      // [n_int][M][8] (coefficients 0..5, two zero pads)
     double *nodes = nullptr;     // scratch [n_int+1][M][3] of node values g, g', g''
+    // tanh of the fitting net in the FP32 and mixed modes: native, or the
+    // second-order table [kTanhN][a0, a1, a2, 0] on [0, 8)
+    float *tanh_tab = nullptr;
+    int tanh_on = 0;
 };
 
 struct dp_nlist {
@@ -179,6 +183,8 @@ void launch_fill_zero(double *p, long n, hipStream_t st);
 void launch_fill_zero_bytes(void *p, size_t nbytes, hipStream_t st);
 void launch_fill_zero_int(int *p, long n, hipStream_t st);
 dp_status launch_tabulate(dp_model *m, hipStream_t st);
+constexpr int kTanhN = 1024;   // tanh table intervals of width 1/128 on [0, 8)
+void launch_tanh_table(float *tab, hipStream_t st);
 dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, const int *types,
                              bool reset_flags, hipStream_t st);
 // Candidates of the atoms [off, off + n) of a batch, all inside one cell with
@@ -219,6 +225,7 @@ struct Epi {
     void *out_t;       // TR[M][N]
     int resw = 0;      // EPI_EMB: width of the residual input
     int half = 0;      // EPI_FOLD
+    const float *tanh_tab = nullptr;   // FP32 epilogues: tanh from this table (kTanhN x 4), or native
 };
 template <typename TA, typename TR>
 void launch_gemm(int epi, int M, int N, int K, const TA *A, const TA *Bt, const Epi &e, hipStream_t st);

@@ -80,6 +80,22 @@ template <> __device__ inline __bf16 tod<__bf16>(double v) { return (__bf16)(flo
 __device__ inline float tanh_r(float v) { return tanhf(v); }
 __device__ inline double tanh_r(double v) { return tanh(v); }
 
+// tanh of an FP32 epilogue: native, or from the second-order table on
+// [0, 8) (odd extension, 1 beyond 8); FP64 epilogues always take tanh.
+__device__ inline float tanh_e(float x, const float *tab)
+{
+    if (!tab) return tanhf(x);
+    float ax = fabsf(x);
+    if (ax >= 8.f) return copysignf(1.f, x);
+    int k = (int)(ax * (kTanhN / 8.f));
+    k = k < kTanhN - 1 ? k : kTanhN - 1;
+    float t = ax - k * (8.f / kTanhN);
+    float4 a = *reinterpret_cast<const float4 *>(tab + 4 * k);
+    float y = fmaf(t, fmaf(t, a.z, a.y), a.x);
+    return copysignf(y, x);
+}
+__device__ inline double tanh_e(double x, const float *) { return tanh(x); }
+
 }  // namespace
 
 namespace {
@@ -206,17 +222,17 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const TA *
                 if constexpr (EPI == EPI_LIN) {
                     ((TR *)e.out_r)[idx] = v;
                 } else if constexpr (EPI == EPI_T1) {
-                    TR y = tanh_r(v + bias[gn]);
+                    TR y = tanh_e(v + bias[gn], e.tanh_tab);
                     ((TR *)e.out_r)[idx] = y;
                     if (e.out_o) store_op((TA *)e.out_o, gm, gn, N, (double)y);
                 } else if constexpr (EPI == EPI_T2) {
-                    TR t = tanh_r(v + bias[gn]);
+                    TR t = tanh_e(v + bias[gn], e.tanh_tab);
                     TR y = ((const TR *)e.res)[idx] + t;
                     ((TR *)e.out_t)[idx] = t;
                     ((TR *)e.out_r)[idx] = y;
                     if (e.out_o) store_op((TA *)e.out_o, gm, gn, N, (double)y);
                 } else if constexpr (EPI == EPI_T3) {
-                    ((TR *)e.out_t)[idx] = tanh_r(v + bias[gn]);
+                    ((TR *)e.out_t)[idx] = tanh_e(v + bias[gn], e.tanh_tab);
                 } else if constexpr (EPI == EPI_EMB) {
                     TR t = tanh_r(v + bias[gn]);
                     ((TR *)e.out_t)[idx] = t;

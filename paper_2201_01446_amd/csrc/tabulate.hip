@@ -120,4 +120,30 @@ dp_status launch_tabulate(dp_model *m, hipStream_t st)
     return DP_OK;
 }
 
+namespace {
+
+// tanh on [0, 8) by a quadratic per interval of width 1/128: the value and
+// slope of tanh at the left node x0 and its value at x0 + h (paper Sec. 3.5
+// fixes the order, the range, the odd extension and the saturation at 8).
+__global__ void k_tanh_table(float *tab)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= kTanhN) return;
+    const double h = 8.0 / kTanhN;
+    double x0 = k * h;
+    double a0 = tanh(x0), a1 = 1.0 - a0 * a0;
+    double a2 = (tanh(x0 + h) - a0 - a1 * h) / (h * h);
+    tab[4 * k] = (float)a0;
+    tab[4 * k + 1] = (float)a1;
+    tab[4 * k + 2] = (float)a2;
+    tab[4 * k + 3] = 0.f;
+}
+
+}  // namespace
+
+void launch_tanh_table(float *tab, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tanh_table, dim3(div_up(kTanhN, 256)), dim3(256), 0, st, tab);
+}
+
 }  // namespace dp

@@ -500,3 +500,48 @@ def test_nve_energy_error_scales_with_dt_squared(orc, cu_cfg):
         assert abs(et[-1] - et[0]) <= dev[-1]
     assert 3.5 < dev[0] / dev[1] < 4.5, dev
     assert dev[0] < 1e-3 * rows[0, 1]
+
+
+# ---------------------------------------------------------- tabulated tanh
+
+def test_tanh_table_error_bound(orc):
+    """Second-order table on [0, 8): value and slope at the left node, value
+    at the right node.  Its error is f'''(xi)/6 t^2 (t - h), at most
+    (4/27)(h^3/6) max|tanh'''| = (4/27)(h^3/6) 2 inside the range; beyond 8
+    it is 1 - tanh(x) (the saturation the paper states); odd exactly."""
+    h = 1.0 / 128.0
+    x = np.linspace(0.0, 8.0, 256001)[:-1]
+    e = np.abs(orc.tanh_table(x) - np.tanh(x))
+    bound = 4.0 / 27.0 * h ** 3 / 6.0 * 2.0
+    assert e.max() <= 1.001 * bound
+    assert e.max() > 0.5 * bound          # the bound is attained near 0, where |tanh'''| = 2
+    nodes = np.arange(0, 1024) * h
+    np.testing.assert_allclose(orc.tanh_table(nodes), np.tanh(nodes), rtol=0, atol=3e-16)   # libm vs numpy: 1 ulp
+    right = nodes[1:] - 1e-13             # value at the right node is matched too
+    assert np.max(np.abs(orc.tanh_table(right) - np.tanh(right))) < 1e-12
+    big = np.array([8.0, 9.5, 40.0])
+    assert np.all(orc.tanh_table(big) == 1.0)
+    assert abs(orc.tanh_table(np.array([8.0]))[0] - np.tanh(8.0)) == pytest.approx(1 - np.tanh(8.0), rel=1e-9)
+    xs = np.linspace(-10, 10, 2001)
+    np.testing.assert_array_equal(orc.tanh_table(-xs), -orc.tanh_table(xs))
+
+
+def test_tanh_table_in_fitting_net(orc, cu_cfg, cu_params):
+    """The option switches only the fitting net's tanh: a dimer (where the
+    embedding is untouched) changes by the table's error times the fitting
+    net's sensitivity, and the forces stay -dE/dx by central differences."""
+    import synth
+    cfg = dict(cu_cfg, tanh_table=1)
+    x, box = synth.copper(2, 0.1, 5)
+    a = orc.evaluate(cu_cfg, cu_params, x, box)
+    b = orc.evaluate(cfg, cu_params, x, box)
+    dE = abs(a["E"] - b["E"]) / len(x)
+    assert 0 < dE < 1e-5
+    hstep = 1e-5
+    for (i, c) in ((0, 0), (7, 2)):
+        xp, xm = x.copy(), x.copy()
+        xp[i, c] += hstep
+        xm[i, c] -= hstep
+        fd = (orc.evaluate(cfg, cu_params, xp, box)["E"] - orc.evaluate(cfg, cu_params, xm, box)["E"]) / (2 * hstep)
+        # the backward takes 1 - y^2 of the tabulated y, not the table's own slope: agreement to the table error
+        assert abs(-b["F"][i, c] - fd) <= 1e-6 * np.max(np.abs(b["F"])) + 1e-9
