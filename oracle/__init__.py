@@ -42,6 +42,8 @@ class Config(ctypes.Structure):
         ("desc_scale", ctypes.c_double),
         ("switch_kind", ctypes.c_int),
         ("tanh_table", ctypes.c_int),
+        ("ntypes", ctypes.c_int),
+        ("sel_t", ctypes.c_int * 4),
     ]
 
 
@@ -63,16 +65,16 @@ def lib():
         L.orc_switch.argtypes = [pc, d, pd, pd]
         L.orc_tanh_table.argtypes = [d]
         L.orc_tanh_table.restype = d
-        L.orc_embed.argtypes = [pc, pd, d, pd, pd, pd]
+        L.orc_embed.argtypes = [pc, pd, i, d, pd, pd, pd]
         L.orc_hermite.argtypes = [d, d, d, d, d, d, d, pd]
         L.orc_table_intervals.argtypes = [d, d, d, d]
         L.orc_table_intervals.restype = i
-        L.orc_tabulate.argtypes = [pc, pd, d, d, d, d, pd]
+        L.orc_tabulate.argtypes = [pc, pd, i, d, d, d, d, pd]
         L.orc_tabulate.restype = i
         L.orc_table_eval.argtypes = [pc, i, i, d, d, d, d, pd, d, pd, pd]
         L.orc_neighbors.argtypes = [pc, i, pd, pd, i, i, pi, pi, pd]
         L.orc_neighbors.restype = i
-        L.orc_evaluate.argtypes = [pc, pd, i, pd, pd, i, pi, i, i, d, d, d, d, pd,
+        L.orc_evaluate.argtypes = [pc, pd, i, pd, pd, pi, i, pi, i, i, d, d, d, d, pd,
                                    pd, pd, pd, pi, pd, pd, pl]
         L.orc_evaluate.restype = l
         L.orc_num_threads.restype = i
@@ -90,7 +92,8 @@ def _ip(a):
 
 def make_config(cfg):
     """cfg: mapping with rcut, rcut_smth, sel, emb (3), m_lt, fit (3), desc_scale, switch_kind and,
-    optionally, tanh_table (1: the fitting net's tanh from the second-order table)."""
+    optionally, tanh_table (1: the fitting net's tanh from the second-order table) and, for
+    several atom types, ntypes and sel_t (neighbors kept per neighbor type; sel = their sum)."""
     c = Config()
     c.rcut = cfg["rcut"]
     c.rcut_smth = cfg["rcut_smth"]
@@ -101,7 +104,14 @@ def make_config(cfg):
     c.desc_scale = cfg["desc_scale"]
     c.switch_kind = cfg.get("switch_kind", 0)
     c.tanh_table = cfg.get("tanh_table", 0)
+    c.ntypes = cfg.get("ntypes", 1)
+    for t, v in enumerate(cfg.get("sel_t", ())):
+        c.sel_t[t] = v
     return c
+
+
+def ntypes(cfg):
+    return max(1, cfg.get("ntypes", 1))
 
 
 def param_count(cfg):
@@ -116,13 +126,13 @@ def switch(cfg, r):
     return w.value, dw.value
 
 
-def embed(cfg, params, s):
-    """G(s), G'(s), G''(s) of the embedding net (Eqs. 3-5)."""
+def embed(cfg, params, s, ntype=0):
+    """G(s), G'(s), G''(s) of the embedding net of neighbor type ntype (Eqs. 3-5)."""
     c = make_config(cfg)
     p = np.ascontiguousarray(params, dtype=np.float64)
     M = cfg["emb"][2]
     G, dG, ddG = (np.zeros(M) for _ in range(3))
-    lib().orc_embed(ctypes.byref(c), _dp(p), float(s), _dp(G), _dp(dG), _dp(ddG))
+    lib().orc_embed(ctypes.byref(c), _dp(p), int(ntype), float(s), _dp(G), _dp(dG), _dp(ddG))
     return G, dG, ddG
 
 
@@ -134,26 +144,33 @@ def hermite(y0, d0, dd0, y1, d1, dd1, h):
 
 
 class Table:
-    """A tabulated embedding net (Sec. 3.2): coef[theta, eta, xi]."""
+    """Tabulated embedding nets (Sec. 3.2), one per neighbor type, back to
+    back: coef[type * n + theta, eta, xi] (n intervals per type)."""
 
     def __init__(self, cfg, params, s_max, h, tail_max, h_tail):
         c = make_config(cfg)
         n = lib().orc_table_intervals(s_max, h, tail_max, h_tail)
         M = cfg["emb"][2]
-        self.coef = np.zeros((n, M, 6))
+        T = ntypes(cfg)
+        self.coef = np.zeros((T * n, M, 6))
         p = np.ascontiguousarray(params, dtype=np.float64)
-        lib().orc_tabulate(ctypes.byref(c), _dp(p), s_max, h, tail_max, h_tail, _dp(self.coef))
+        for t in range(T):
+            part = np.zeros((n, M, 6))
+            lib().orc_tabulate(ctypes.byref(c), _dp(p), t, s_max, h, tail_max, h_tail, _dp(part))
+            self.coef[t * n:(t + 1) * n] = part
+        self.n_int = n
         self.n_fine = int(round(s_max / h))
         self.n_tail = n - self.n_fine
         self.h, self.s_max, self.h_tail, self.tail_max = h, s_max, h_tail, tail_max
         self.cfg = cfg
 
-    def eval(self, s):
+    def eval(self, s, ntype=0):
         c = make_config(self.cfg)
         M = self.cfg["emb"][2]
         G, dG = np.zeros(M), np.zeros(M)
+        part = np.ascontiguousarray(self.coef[ntype * self.n_int:(ntype + 1) * self.n_int])
         lib().orc_table_eval(ctypes.byref(c), self.n_fine, self.n_tail, self.h, self.s_max,
-                             self.h_tail, self.tail_max, _dp(self.coef), float(s), _dp(G), _dp(dG))
+                             self.h_tail, self.tail_max, _dp(part), float(s), _dp(G), _dp(dG))
         return G, dG
 
 
@@ -170,11 +187,12 @@ def neighbors(cfg, coords, box, i, cap=4096):
     return j[:m], img[:m], r[:m], n
 
 
-def evaluate(cfg, params, coords, box, table=None, centers=None, forces=True, desc=False):
+def evaluate(cfg, params, coords, box, table=None, centers=None, forces=True, desc=False, types=None):
     """Energy, per-atom energy, forces and virial.
 
     centers: optional index array; then e_atom is per listed center and the
-    force holds only those centers' contributions.
+    force holds only those centers' contributions.  types: per-atom type
+    (None: all type 0).
     Returns a dict with E, e_atom, F, W (3x3), nnei, dropped, table_oob and,
     when desc is set, T (n,4,M) and D (n, M<*M).
     """
@@ -183,6 +201,9 @@ def evaluate(cfg, params, coords, box, table=None, centers=None, forces=True, de
     N = x.shape[0]
     b = None if box is None else np.ascontiguousarray(box, dtype=np.float64).reshape(9)
     cen = None if centers is None else np.ascontiguousarray(centers, dtype=np.int32)
+    typ = None if types is None else np.ascontiguousarray(types, dtype=np.int32)
+    if typ is not None and (typ.shape != (N,) or typ.min() < 0 or typ.max() >= ntypes(cfg)):
+        raise ValueError("types must hold one type in [0, ntypes) per atom")
     nc = N if cen is None else cen.shape[0]
     M, Ml = cfg["emb"][2], cfg["m_lt"]
     p = np.ascontiguousarray(params, dtype=np.float64)
@@ -197,7 +218,7 @@ def evaluate(cfg, params, coords, box, table=None, centers=None, forces=True, de
         tab = (0, 0, 1.0, 0.0, 1.0, 0.0, None)
     else:
         tab = (table.n_fine, table.n_tail, table.h, table.s_max, table.h_tail, table.tail_max, _dp(table.coef))
-    dropped = lib().orc_evaluate(ctypes.byref(c), _dp(p), N, _dp(x), _dp(b), nc, _ip(cen), *tab,
+    dropped = lib().orc_evaluate(ctypes.byref(c), _dp(p), N, _dp(x), _dp(b), _ip(typ), nc, _ip(cen), *tab,
                                  _dp(e_atom), _dp(F), _dp(W), _ip(nnei), _dp(T), _dp(D), ctypes.byref(oob))
     if dropped < 0:
         raise MemoryError("oracle allocation failed")
@@ -221,23 +242,26 @@ ACC_UNIT = 9.64853321e-3
 KE_UNIT = 103.642691
 
 
-def velocity_verlet(cfg, params, x, v, box, mass, dt, nsteps, table=None):
+def velocity_verlet(cfg, params, x, v, box, mass, dt, nsteps, table=None, types=None):
     """Plain velocity-Verlet NVE (the MD protocol of the paper's
-    physical-systems section): half kick, drift, force, half kick.
-    Returns (x, v, rows) with rows[t] = (PE, KE) after step t (t = 0 is the
-    start)."""
+    physical-systems section): half kick, drift, force, half kick.  mass is
+    one number or one per atom.  Returns (x, v, rows) with rows[t] = (PE, KE)
+    after step t (t = 0 is the start)."""
     x = np.array(x, dtype=np.float64)
     v = np.array(v, dtype=np.float64)
-    out = evaluate(cfg, params, x, box, table=table)
+    mass = np.asarray(mass, dtype=np.float64)
+    if mass.ndim == 1:
+        mass = mass[:, None]
+    out = evaluate(cfg, params, x, box, table=table, types=types)
     F = out["F"]
-    rows = [(out["E"], 0.5 * mass * KE_UNIT * float(np.sum(v * v)))]
+    rows = [(out["E"], 0.5 * KE_UNIT * float(np.sum(mass * v * v)))]
     for _ in range(nsteps):
         v = v + 0.5 * dt * ACC_UNIT * F / mass
         x = x + dt * v
-        out = evaluate(cfg, params, x, box, table=table)
+        out = evaluate(cfg, params, x, box, table=table, types=types)
         F = out["F"]
         v = v + 0.5 * dt * ACC_UNIT * F / mass
-        rows.append((out["E"], 0.5 * mass * KE_UNIT * float(np.sum(v * v))))
+        rows.append((out["E"], 0.5 * KE_UNIT * float(np.sum(mass * v * v))))
     return x, v, np.array(rows)
 
 

@@ -37,6 +37,12 @@
  *     of its interval; interval index min(floor(s/h), n-1) (left-closed);
  *     beyond the last node s is clamped to the table end;
  *   - more than sel neighbors: keep the sel nearest by (r, j, image);
+ *   - several atom types (the paper's water has two; its text does not
+ *     spell out how types enter): the embedding net is chosen by the
+ *     NEIGHBOR's type, the fitting net by the CENTER's type, and of each
+ *     neighbor type t only the sel_t nearest are kept; the sum over j in
+ *     R^T G runs over all kept neighbors of all types, scaled by
+ *     desc_scale (default 1 / sum_t sel_t);
  *   - virial W = - sum_i sum_j r_ij (x) dE_i/dr_ij;
  *   - tabulated tanh (tanh_table = 1): intervals of width 1/128 on [0, 8);
  *     on [x0, x0 + h] the quadratic with the value and slope of tanh at x0
@@ -54,6 +60,8 @@
 #include <omp.h>
 #endif
 
+#define ORC_MAX_TYPES 4
+
 typedef struct {
     double rcut, rcut_smth;
     int sel;
@@ -63,7 +71,11 @@ typedef struct {
     double desc_scale;   /* factor on R^T G                               */
     int switch_kind;     /* 0 quintic smoothstep, 1 cosine                */
     int tanh_table;      /* 1: tabulated tanh in the fitting net          */
+    int ntypes;          /* atom types (chemical species); <= 1 means one */
+    int sel_t[ORC_MAX_TYPES];  /* neighbors kept per neighbor type (ntypes > 1) */
 } orc_config;
+
+static int n_types(const orc_config *c) { return c->ntypes > 1 ? c->ntypes : 1; }
 
 /* A tabulated embedding net: n_int intervals, each with M quintics in the
  * local variable t = s - lo[theta].  coef[(theta*M + eta)*6 + xi]. */
@@ -99,25 +111,48 @@ static double act(const orc_config *c, double z) { return c->tanh_table ? orc_ta
 
 typedef struct {
     const double *W0, *b0, *W1, *b1, *W2, *b2;          /* embedding */
+} orc_emb_params;
+typedef struct {
     const double *V1, *c1, *V2, *c2, *V3, *c3, *w4, *b4; /* fitting   */
-} orc_params;
+} orc_fit_params;
 
-long orc_param_count(const orc_config *c)
+static long emb_count(const orc_config *c)
 {
-    long dD = (long)c->m_lt * c->d3;
-    return (long)1 * c->d1 + c->d1 + (long)c->d1 * c->d2 + c->d2 + (long)c->d2 * c->d3 + c->d3 +
-           dD * c->f1 + c->f1 + (long)c->f1 * c->f2 + c->f2 + (long)c->f2 * c->f3 + c->f3 + c->f3 + 1;
+    return (long)1 * c->d1 + c->d1 + (long)c->d1 * c->d2 + c->d2 + (long)c->d2 * c->d3 + c->d3;
 }
 
-static orc_params split_params(const orc_config *c, const double *p)
+static long fit_count(const orc_config *c)
 {
-    orc_params q;
+    long dD = (long)c->m_lt * c->d3;
+    return dD * c->f1 + c->f1 + (long)c->f1 * c->f2 + c->f2 + (long)c->f2 * c->f3 + c->f3 + c->f3 + 1;
+}
+
+/* The parameter vector holds one embedding net per neighbor type, then one
+ * fitting net per center type (types in increasing order). */
+long orc_param_count(const orc_config *c)
+{
+    return n_types(c) * (emb_count(c) + fit_count(c));
+}
+
+/* Embedding net applied to neighbors of type t. */
+static orc_emb_params emb_params(const orc_config *c, const double *p, int t)
+{
+    orc_emb_params q;
+    p += t * emb_count(c);
     q.W0 = p; p += c->d1;
     q.b0 = p; p += c->d1;
     q.W1 = p; p += (long)c->d1 * c->d2;
     q.b1 = p; p += c->d2;
     q.W2 = p; p += (long)c->d2 * c->d3;
-    q.b2 = p; p += c->d3;
+    q.b2 = p;
+    return q;
+}
+
+/* Fitting net of centers of type t. */
+static orc_fit_params fit_params(const orc_config *c, const double *p, int t)
+{
+    orc_fit_params q;
+    p += n_types(c) * emb_count(c) + t * fit_count(c);
     q.V1 = p; p += (long)c->m_lt * c->d3 * c->f1;
     q.c1 = p; p += c->f1;
     q.V2 = p; p += (long)c->f1 * c->f2;
@@ -149,13 +184,13 @@ void orc_switch(const orc_config *c, double r, double *w, double *dw)
 
 /* ------------------------------------------- embedding net, Eqs. 3-5 */
 
-/* G(s) and its first two derivatives by forward-mode differentiation.
- * Any of G, dG, ddG may be NULL.  Layer 0: tanh(s W0 + b0); layers 1, 2:
+/* G(s) of the embedding net of neighbor type `type` and its first two
+ * derivatives by forward-mode differentiation.  Any of G, dG, ddG may be NULL.  Layer 0: tanh(s W0 + b0); layers 1, 2:
  * [x, x] + tanh(x W + b). */
-void orc_embed(const orc_config *c, const double *params, double s,
+void orc_embed(const orc_config *c, const double *params, int type, double s,
                double *G, double *dG, double *ddG)
 {
-    orc_params q = split_params(c, params);
+    orc_emb_params q = emb_params(c, params, type);
     int d1 = c->d1, d2 = c->d2, d3 = c->d3;
     double *h = malloc(sizeof(double) * 3 * d3);
     double *hn = malloc(sizeof(double) * 3 * d3);
@@ -242,8 +277,9 @@ static double table_node(const orc_table *t, int theta)
     return t->s_max + (theta - t->n_fine) * t->h_tail;
 }
 
-/* Fills coef[(theta*M + eta)*6 + xi]; returns the interval count. */
-int orc_tabulate(const orc_config *c, const double *params, double s_max, double h,
+/* Table of the embedding net of neighbor type `type`: fills
+ * coef[(theta*M + eta)*6 + xi]; returns the interval count. */
+int orc_tabulate(const orc_config *c, const double *params, int type, double s_max, double h,
                  double tail_max, double h_tail, double *coef)
 {
     orc_table t;
@@ -263,8 +299,8 @@ int orc_tabulate(const orc_config *c, const double *params, double s_max, double
         }
         double *g0 = malloc(sizeof(double) * 6 * M);
         double *g1 = g0 + M, *g2 = g0 + 2 * M, *G0 = g0 + 3 * M, *G1 = g0 + 4 * M, *G2 = g0 + 5 * M;
-        orc_embed(c, params, lo, g0, g1, g2);
-        orc_embed(c, params, hi, G0, G1, G2);
+        orc_embed(c, params, type, lo, g0, g1, g2);
+        orc_embed(c, params, type, hi, G0, G1, G2);
         for (int e = 0; e < M; e++)
             orc_hermite(g0[e], g1[e], g2[e], G0[e], G1[e], G2[e], w,
                         coef + ((long)th * M + e) * 6);
@@ -422,14 +458,17 @@ int orc_neighbors(const orc_config *c, int natoms, const double *x, const double
 
 /* ------------------------------------------------- one atom, Eqs. 1-5 */
 
-/* Energy E_i of one atom from its neighbor displacements d[nn][3], and
- * g[nn][3] = dE_i / d r_ij.  T (4 x M) and D (M< x M) are written when not
- * NULL.  tab == NULL: embedding net evaluated directly; else by the table.
- * Returns the number of table look-ups past the table end. */
-static int atom_eval(const orc_config *c, const orc_params *q, const double *params,
-                     const orc_table *tab, int nn, const double (*d)[3],
+/* Energy E_i of one atom of type ctype from its neighbor displacements
+ * d[nn][3] and the neighbors' types ntype[nn], and g[nn][3] = dE_i / d r_ij.
+ * T (4 x M) and D (M< x M) are written when not NULL.  tabs == NULL: the
+ * embedding nets are evaluated directly; else by tabs[type] (one table per
+ * neighbor type).  Returns the number of table look-ups past the table end. */
+static int atom_eval(const orc_config *c, const double *params, const orc_table *tabs,
+                     int nn, const double (*d)[3], const int *ntype, int ctype,
                      double *E, double (*g)[3], double *T_out, double *D_out)
 {
+    orc_fit_params fq = fit_params(c, params, ctype);
+    const orc_fit_params *q = &fq;
     int M = c->d3, Ml = c->m_lt, f1 = c->f1, f2 = c->f2, f3 = c->f3;
     double sig = c->desc_scale;
     int nD = Ml * M;
@@ -457,12 +496,12 @@ static int atom_eval(const orc_config *c, const orc_params *q, const double *par
         for (int a = 0; a < 3; a++) u[4 * j + 1 + a] = d[j][a] / r;
         for (int k = 0; k < 4; k++) R[4 * j + k] = s[j] * u[4 * j + k];
         /* Eqs. 3-5 (or the table of Sec. 3.2) */
-        if (tab) {
+        if (tabs) {
             int oob;
-            table_eval(tab, s[j], G + (size_t)j * M, dG + (size_t)j * M, &oob);
+            table_eval(&tabs[ntype[j]], s[j], G + (size_t)j * M, dG + (size_t)j * M, &oob);
             oob_total += oob;
         } else {
-            orc_embed(c, params, s[j], G + (size_t)j * M, dG + (size_t)j * M, NULL);
+            orc_embed(c, params, ntype[j], s[j], G + (size_t)j * M, dG + (size_t)j * M, NULL);
         }
     }
     /* T = sig * R^T G  (4 x M) */
@@ -577,30 +616,59 @@ static int atom_eval(const orc_config *c, const orc_params *q, const double *par
 
 /* ------------------------------------------------ whole configurations */
 
+/* Keeps, of the sorted neighbor list nb[0..n), the nearest sel of each
+ * neighbor type (one type: the nearest sel), in place and in order; fills
+ * their types and returns how many were kept. */
+static int select_neighbors(const orc_config *c, const int *types, orc_nbr *nb, int n, int *ntype)
+{
+    int T = n_types(c), taken[ORC_MAX_TYPES] = {0}, nn = 0;
+    for (int k = 0; k < n; k++) {
+        int t = types ? types[nb[k].j] : 0;
+        int lim = T > 1 ? c->sel_t[t] : c->sel;
+        if (taken[t] >= lim) continue;
+        taken[t]++;
+        nb[nn] = nb[k];
+        ntype[nn] = t;
+        nn++;
+    }
+    return nn;
+}
+
 /* Evaluates the atoms listed in `centers` (all atoms when centers == NULL,
- * ncent ignored).  Outputs (NULL to skip):
+ * ncent ignored).  types[natoms] gives each atom's type (NULL: all type 0).
+ * Outputs (NULL to skip):
  *   e_atom[ncent]        E_i of each center
  *   force[natoms*3]      contributions -grad E_i of the centers only
  *                        (the full force when every atom is a center)
  *   virial[9]            - sum over centers of sum_j r_ij (x) dE_i/dr_ij
  *   nnei[ncent]          neighbor count within rc (before truncation to sel)
  *   T_out[ncent*4*M], D_out[ncent*M<*M]
- * tab_* describe the table (tab_coef == NULL: untabulated).
+ * tab_* describe the tables (tab_coef == NULL: untabulated); tab_coef holds
+ * one table per neighbor type, back to back.
  * Returns the total number of neighbors dropped by the sel truncation, or -1
  * on an allocation failure. */
 long orc_evaluate(const orc_config *c, const double *params, int natoms, const double *x,
-                  const double *box, int ncent, const int *centers,
+                  const double *box, const int *types, int ncent, const int *centers,
                   int tab_n_fine, int tab_n_tail, double tab_h, double tab_s_max,
                   double tab_h_tail, double tab_tail_max, const double *tab_coef,
                   double *e_atom, double *force, double *virial, int *nnei,
                   double *T_out, double *D_out, long *table_oob)
 {
-    orc_params q = split_params(c, params);
-    orc_table tab = {tab_n_fine, tab_n_tail, tab_h, tab_s_max, tab_h_tail, tab_tail_max,
-                     c->d3, tab_coef};
-    const orc_table *tp = tab_coef ? &tab : NULL;
+    int T = n_types(c), M = c->d3;
+    orc_table tabs[ORC_MAX_TYPES];
+    long per_type = (long)(tab_n_fine + tab_n_tail) * M * 6;
+    for (int t = 0; t < T; t++) {
+        orc_table tb = {tab_n_fine, tab_n_tail, tab_h, tab_s_max, tab_h_tail, tab_tail_max,
+                        M, tab_coef ? tab_coef + t * per_type : NULL};
+        tabs[t] = tb;
+    }
+    const orc_table *tp = tab_coef ? tabs : NULL;
     int nc = centers ? ncent : natoms;
-    int sel = c->sel, M = c->d3;
+    int sel = 0;
+    if (T > 1)
+        for (int t = 0; t < T; t++) sel += c->sel_t[t];
+    else
+        sel = c->sel;
     int cap = 4096;  /* neighbors scanned per atom; far above any sel here */
     long dropped = 0, oob = 0;
     if (force) memset(force, 0, sizeof(double) * 3 * (size_t)natoms);
@@ -622,14 +690,16 @@ long orc_evaluate(const orc_config *c, const double *params, int natoms, const d
             int n = find_neighbors(c, natoms, x, box, i, mine, cap);
             if (n > cap) n = cap;   /* cap far exceeds any neighbor count here */
             if (nnei) nnei[c0 + k] = n;
-            int nn = n < sel ? n : sel;
+            int *ntype = malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+            int nn = select_neighbors(c, types, mine, n, ntype);
             drop_c += n - nn;
             cnt[k] = nn;
             double (*d)[3] = malloc(sizeof(double) * 3 * (size_t)(nn > 0 ? nn : 1));
             for (int j = 0; j < nn; j++)
                 for (int a = 0; a < 3; a++) d[j][a] = mine[j].d[a];
             double Ei;
-            oob_c += atom_eval(c, &q, params, tp, nn, (const double (*)[3])d, &Ei,
+            oob_c += atom_eval(c, params, tp, nn, (const double (*)[3])d, ntype,
+                               types ? types[i] : 0, &Ei,
                                (force || virial) ? g + (size_t)k * sel : NULL,
                                T_out ? T_out + (size_t)(c0 + k) * 4 * M : NULL,
                                D_out ? D_out + (size_t)(c0 + k) * c->m_lt * M : NULL);
@@ -642,6 +712,7 @@ long orc_evaluate(const orc_config *c, const double *params, int natoms, const d
                         for (int b = 0; b < 3; b++)
                             w[3 * a + b] -= d[j][a] * g[(size_t)k * sel + j][b];
             free(d);
+            free(ntype);
         }
         dropped += drop_c;
         oob += oob_c;
