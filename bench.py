@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--no-strides", action="store_true", help="skip the table-stride sweep")
     ap.add_argument("--no-ablation", action="store_true", help="skip the optimization ladder")
     ap.add_argument("--no-tanh", action="store_true", help="skip the tabulated-tanh comparison")
+    ap.add_argument("--no-water", action="store_true", help="skip the two-type water system")
+    ap.add_argument("--water-rep", type=int, default=8, help="replicas per edge of the 192-atom water cell")
     ap.add_argument("--ablation-steps", type=int, default=10)
     ap.add_argument("--stride-steps", type=int, default=20)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -82,13 +84,14 @@ def parse():
     return ap.parse_args()
 
 
-def run_nve(P, model, x0, v0, box, steps, warmup, precision, mode=0, keep=False):
+def run_nve(P, model, x0, v0, box, steps, warmup, precision, mode=0, keep=False, types=None, mass=63.546, dt=1.0):
     import torch
     x = torch.tensor(x0, dtype=torch.float64, device="cuda")
     v = torch.tensor(v0, dtype=torch.float64, device="cuda")
-    nl = P.NeighborList(model, x, box, skin=2.0)
+    td = None if types is None else torch.tensor(types, dtype=torch.int32, device="cuda")
+    nl = P.NeighborList(model, x, box, skin=2.0, types=td)
     if warmup:
-        P.nve_run(model, nl, x, v, box, 63.546, 1.0, warmup, rebuild_every=10, precision=precision, mode=mode)
+        P.nve_run(model, nl, x, v, box, mass, dt, warmup, rebuild_every=10, precision=precision, mode=mode, types=td)
     torch.cuda.synchronize()
     from paper_2201_01446_amd import _lib
     _lib.timers_read()
@@ -98,7 +101,7 @@ def run_nve(P, model, x0, v0, box, steps, warmup, precision, mode=0, keep=False)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     t0.record()
-    th = P.nve_run(model, nl, x, v, box, 63.546, 1.0, steps, rebuild_every=10, precision=precision, mode=mode)
+    th = P.nve_run(model, nl, x, v, box, mass, dt, steps, rebuild_every=10, precision=precision, mode=mode, types=td)
     t1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
@@ -247,9 +250,46 @@ def main():
         out["stride_sweep"] = stride_sweep(P, cfg, params, x0, v0, box, args.stride_steps)
     if not args.no_serve:
         out["serving"] = serving(P, model, args.serve_requests)
+    if not args.no_water:
+        out["water"] = water(P, args.water_rep, min(K, 50), W)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out))
+
+
+def water(P, nrep, steps, warmup):
+    """The two-type system (the paper's water: O and H, rcut 6 A, NVE at
+    0.5 fs): the synthetic 192-atom cell replicated nrep^3 times, in the
+    three precisions."""
+    import synth
+    cfg = synth.water_model_config()
+    params = synth.model_params(cfg)
+    model = P.Model(cfg, params).tabulate(0.7, 0.01, 1.5, 0.1)
+    x0, t, box = synth.water(nrep, sigma=0.05)
+    m = synth.water_masses(t)
+    rng = np.random.Generator(np.random.PCG64(synth.SEED_VELOCITY))
+    v0 = rng.standard_normal(x0.shape) * np.sqrt(synth.KB_EV * 330.0 / (m[:, None] * synth.MVV_TO_EV))
+    v0 -= (m[:, None] * v0).sum(0) / m.sum()
+    N = len(x0)
+    out = {"workload": f"water-like O/H, 192-atom cell x {nrep}^3 ({N} atoms), NVE dt 0.5 fs, sel 46 O + 92 H, "
+                       "nlist skin 2 A rebuilt every 10 steps, compressed (stride 0.01, tail 0.1)",
+           "natoms": N, "steps": steps}
+    for name, prec in (("fp32", P.FP32), ("fp64", P.FP64), ("mixed_bf16", P.MIXED_BF16)):
+        res = run_nve(P, model, x0, v0, box, steps, warmup, prec, types=t, mass=[synth.M_O, synth.M_H], dt=0.5,
+                      keep=(name == "fp32"))
+        v = N * steps / (res["ms"] * 1e-3)
+        th = res["thermo"]
+        etot = th[:, 0] + th[:, 1]
+        out[name] = {"value": round(v, 1), "unit": "atom-steps/s", "ms_per_step": round(res["ms"] / steps, 4),
+                     "ns_per_day": round(v / N * 86400 * 0.5e-6, 3),
+                     "energy_drift_eV_per_atom": float((etot[-1] - etot[0]) / N),
+                     "kernels": {k: round(vv[0] / max(vv[1], 1), 4) for k, vv in res["kernels"].items()}}
+        if name == "fp32":
+            d = P.descriptor(model, res["nl"], res["x"], precision=P.FP32)
+            out["mean_neighbors"] = float(d["nnei"].double().mean().item())
+            out["mean_interval_segments"] = float(d["nseg"].double().mean().item())
+            del res
+    return out
 
 
 def tanh_compare(P, cfg, params, x0, v0, box, steps):

@@ -65,14 +65,21 @@ typedef enum {
 } dp_mode;
 
 /* Model hyper-parameters (Sec. 2.1 and the physical-systems section).
- *   ntypes      must be 1 (one element, copper);
+ *   ntypes      atom types (chemical species), 1..DP_MAX_TYPES: copper has
+ *               one, water two (O, H).  With several types the embedding net
+ *               is chosen by the neighbor's type and the fitting net by the
+ *               center's type;
  *   rcut        cut-off R_c (A); rcut_smth: start of the gate w(r) (A);
  *   sel         N_m: neighbors kept per atom (the nearest sel within rcut), 1..512;
+ *               with several types the sum of sel_t;
+ *   sel_t       (ntypes > 1) neighbors kept per neighbor type: of each type t
+ *               the nearest sel_t within rcut; each >= 1;
  *   emb         embedding widths d1, 2 d1, 4 d1 (M = emb[2]); emb[2] must be 128;
  *   m_lt        M<, columns of G kept in G< (Eq. 2); must be 16;
  *   fit         fitting-net hidden widths (each at most 256);
  *   desc_scale  factor multiplying R^T G (1/sel by default);
  *   switch_kind 0: gate 1-10u^3+15u^4-6u^5, 1: (cos(pi u)+1)/2, u=(r-rs)/(rc-rs). */
+#define DP_MAX_TYPES 4
 typedef struct {
     int ntypes;
     double rcut;
@@ -83,13 +90,16 @@ typedef struct {
     int fit[3];
     double desc_scale;
     int switch_kind;
+    int sel_t[DP_MAX_TYPES];
 } dp_model_config;
 
 typedef struct dp_model dp_model;
 typedef struct dp_nlist dp_nlist;
 
 /* Creates a model from the flat FP64 parameter vector params_h (HOST,
- * nparams doubles, copied).  Layout, row-major [fan_in][fan_out]:
+ * nparams doubles, copied).  Layout, row-major [fan_in][fan_out]: ntypes
+ * embedding nets (for neighbors of type 0, 1, ...), then ntypes fitting nets
+ * (for centers of type 0, 1, ...), each
  *   embedding  W0[1][d1] b0[d1] W1[d1][2d1] b1[2d1] W2[2d1][4d1] b2[4d1]
  *   fitting    V1[M< * M][f1] c1[f1] V2[f1][f2] c2[f2] V3[f2][f3] c3[f3]
  *              w4[f3] b4[1]
@@ -97,13 +107,13 @@ typedef struct dp_nlist dp_nlist;
  * concatenation [x, x]); fitting layers are tanh with a shortcut where the
  * input and output widths match, and a linear output (Sec. 2.1).
  * Allocates device memory on the current device.  Errors: DP_ERR_ARG on a
- * bad config or count, DP_ERR_UNSUPPORTED for ntypes != 1 or other widths. */
+ * bad config or count, DP_ERR_UNSUPPORTED for other widths or ntypes. */
 dp_status dp_model_create(const dp_model_config *cfg, const double *params_h, size_t nparams,
                           dp_model **out);
 dp_status dp_model_destroy(dp_model *model);
 
-/* Builds the coefficient table of the embedding net (Sec. 3.2): on each
- * interval the M quintics whose value, first and second derivative match the
+/* Builds the coefficient table of the embedding net (Sec. 3.2), one per
+ * neighbor type on the same intervals: on each interval the M quintics whose value, first and second derivative match the
  * net at both nodes.  Intervals of width `stride` cover [0, s_max), then
  * intervals of width `tail_stride` cover [s_max, tail_max) (tail_max ==
  * s_max: no tail).  A polynomial is written in the offset t = s - x_lo from
@@ -122,9 +132,10 @@ dp_status dp_tabulate(dp_model *model, double s_max, double stride, double tail_
  * `stream` at the first call with tabulated = 1.  DP_ERR_ARG on other values. */
 dp_status dp_fitting_tanh(dp_model *model, int tabulated, void *stream);
 
-/* Copies the FP64 table to the host: coef_h[(theta * M + eta) * 6 + xi] is
- * the coefficient of t^xi of column eta on interval theta.  *n_int receives
- * the interval count (coef_h may be NULL to query it).  Synchronises. */
+/* Copies the FP64 tables to the host: coef_h[((type * n + theta) * M + eta)
+ * * 6 + xi] is the coefficient of t^xi of column eta on interval theta of the
+ * table of neighbor type `type` (ntypes tables of n intervals).  *n_int
+ * receives n (coef_h may be NULL to query it).  Synchronises. */
 dp_status dp_table_download(dp_model *model, double *coef_h, int *n_int);
 
 /* Neighbor list with a skin (paper Sec. 2.1 L_Rc(i); the MD protocol keeps a
@@ -133,9 +144,12 @@ dp_status dp_table_download(dp_model *model, double *coef_h, int *n_int);
  * device.  Images are handled for any box edge >= (rcut + skin) / 2, so cells
  * smaller than the cut-off sphere see several images of each atom (and of
  * the atom itself).  *inout: NULL creates a list, else it is rebuilt in place
- * (reallocated if natoms grew).  types_d (natoms int32) must be all 0.
+ * (reallocated if natoms grew).  types_d (natoms int32, device) holds each
+ * atom's type in [0, ntypes) (NULL: all 0); with several types every list is
+ * grouped by neighbor type, nearest first within a type, and the list keeps
+ * its own copy of the types (they are fixed for the life of the list).
  * Synchronises once to check the capacity flags; DP_ERR_CAPACITY when an
- * atom has more than 1024 candidates. */
+ * atom has more than 1024 candidates, DP_ERR_ARG for a type out of range. */
 dp_status dp_build_nlist(dp_model *model, int natoms, const double *coords_d, const int *types_d,
                          const double *box_h, double skin, dp_nlist **inout, void *stream);
 dp_status dp_nlist_destroy(dp_nlist *nlist);
@@ -151,7 +165,9 @@ dp_status dp_nlist_destroy(dp_nlist *nlist);
  *   atom_energy_d[natoms]  E_i
  * Passing force_d == NULL and virial_d == NULL runs the forward pass only.
  * mode DP_PLAIN evaluates the embedding net layer by layer over sel padded
- * rows (the untabulated baseline); every other mode needs dp_tabulate first. */
+ * rows (the untabulated baseline); every other mode needs dp_tabulate first.
+ * The types are those the list was built with (types_d is not read).  With
+ * several types, modes DP_PLAIN and DP_TAB_UNFUSED return DP_ERR_UNSUPPORTED. */
 dp_status dp_compute(dp_model *model, dp_nlist *nlist, int natoms, const double *coords_d,
                      const int *types_d, const double *box_h, int mode, int precision,
                      double *energy_d, double *force_d, double *virial_d,
@@ -193,12 +209,14 @@ dp_status dp_nlist_stats(dp_nlist *nlist, int *max_nei, int *n_sel_overflow, int
 /* Velocity-Verlet NVE (the MD protocol of the physical-systems section):
  * nsteps of half kick, drift, [neighbor rebuild every rebuild_every steps],
  * force, half kick, all on `stream` in FP64 (positions x_d and velocities
- * v_d, natoms x 3, updated in place; A and A/fs).  mass in amu, dt_fs in fs.
- * thermo_d (device, nsteps+1 rows of 2 doubles: potential and kinetic
- * energy, row 0 = start) may be NULL.  The nlist is rebuilt at the start.
- * Synchronises at the end to check the capacity flags. */
+ * v_d, natoms x 3, updated in place; A and A/fs).  mass_h (HOST, ntypes
+ * values) is the mass of each type in amu, dt_fs in fs; types_d as for
+ * dp_build_nlist.  thermo_d (device, nsteps+1 rows of 2 doubles: potential
+ * and kinetic energy, row 0 = start) may be NULL.  The nlist is rebuilt at
+ * the start (synchronising once), then every rebuild_every steps on the
+ * stream.  Synchronises at the end to check the capacity flags. */
 dp_status dp_nve_run(dp_model *model, dp_nlist **nlist, int natoms, double *x_d, double *v_d,
-                     const int *types_d, const double *box_h, double mass, double dt_fs,
+                     const int *types_d, const double *box_h, const double *mass_h, double dt_fs,
                      int nsteps, int rebuild_every, double skin, int mode, int precision,
                      double *thermo_d, void *stream);
 
@@ -209,9 +227,10 @@ dp_status dp_nve_run(dp_model *model, dp_nlist **nlist, int natoms, double *x_d,
  * built for its own box into one combined list, every per-atom kernel and
  * fitting-net GEMM runs once over all atoms of the batch, and E and W are
  * reduced per request in an order fixed relative to the request's first atom,
- * so a request's energy and virial do not depend on its batch-mates (forces
- * differ only by the order of FP64 atomic additions).  The batch's neighbor
- * list and scratch are allocated once (for max_atoms) and stay resident. */
+ * so a request's energy and virial do not depend on its batch-mates, nor do
+ * its forces (gathered per atom in a fixed order).  The batch's neighbor
+ * list and scratch are allocated once (for max_atoms) and stay resident.
+ * Batches hold one-type models only (DP_ERR_UNSUPPORTED otherwise). */
 typedef struct {
     int natoms;      /* atoms of this request                                */
     int offset;      /* first atom in the batch (requests are contiguous)    */

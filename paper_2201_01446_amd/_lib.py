@@ -27,7 +27,8 @@ class DPError(RuntimeError):
 class ModelConfig(ctypes.Structure):
     _fields_ = [("ntypes", ctypes.c_int), ("rcut", ctypes.c_double), ("rcut_smth", ctypes.c_double),
                 ("sel", ctypes.c_int), ("emb", ctypes.c_int * 3), ("m_lt", ctypes.c_int),
-                ("fit", ctypes.c_int * 3), ("desc_scale", ctypes.c_double), ("switch_kind", ctypes.c_int)]
+                ("fit", ctypes.c_int * 3), ("desc_scale", ctypes.c_double), ("switch_kind", ctypes.c_int),
+                ("sel_t", ctypes.c_int * 4)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -50,7 +51,7 @@ _SIG = {
     "dp_energy_forward": [_vp, _vp, _i, _vp, _i, _i, _vp, _vp, _vp],
     "dp_energy_backward": [_vp, _vp, _i, _vp, _i, _i, _vp, _vp, _vp],
     "dp_nlist_stats": [_vp, _pi, _pi, _pi, _pi],
-    "dp_nve_run": [_vp, _pvp, _i, _vp, _vp, _vp, _vp, _d, _d, _i, _i, _d, _i, _i, _vp, _vp],
+    "dp_nve_run": [_vp, _pvp, _i, _vp, _vp, _vp, _vp, _vp, _d, _i, _i, _d, _i, _i, _vp, _vp],
     "dp_batch_create": [_vp, _i, _i, _d, _pvp],
     "dp_batch_destroy": [_vp],
     "dp_batch_compute": [_vp, _vp, _i, _vp, _vp, _i, _vp, _vp, _vp, _vp, _vp],

@@ -44,7 +44,9 @@ class Model:
 
     def __init__(self, cfg, params):
         c = ModelConfig()
-        c.ntypes = 1
+        c.ntypes = cfg.get("ntypes", 1)
+        for t, v in enumerate(cfg.get("sel_t", ())):
+            c.sel_t[t] = v
         c.rcut, c.rcut_smth, c.sel = cfg["rcut"], cfg["rcut_smth"], cfg["sel"]
         c.emb[:] = list(cfg["emb"])
         c.m_lt = cfg["m_lt"]
@@ -69,9 +71,10 @@ class Model:
         return self
 
     def table(self):
+        """FP64 coefficients [ntypes * n_int, M, 6] (the types' tables back to back)."""
         n = ctypes.c_int()
         check(lib.dp_table_download(self.h, None, ctypes.byref(n)))
-        out = np.zeros((n.value, self.cfg["emb"][2], 6))
+        out = np.zeros((max(1, self.cfg.get("ntypes", 1)) * n.value, self.cfg["emb"][2], 6))
         check(lib.dp_table_download(self.h, out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
         return out
 
@@ -82,7 +85,8 @@ class Model:
 
 
 class NeighborList:
-    """A neighbor list with skin for one configuration; owns its scratch."""
+    """A neighbor list with skin for one configuration; owns its scratch.
+    types: int32 device tensor of per-atom types (None: all type 0)."""
 
     def __init__(self, model, coords, box=None, skin=2.0, types=None):
         self.h = ctypes.c_void_p()
@@ -93,6 +97,8 @@ class NeighborList:
         n = coords.shape[0]
         _f64(coords, (n, 3))
         b, bp = _box(box)
+        if types is not None and (types.dtype != torch.int32 or tuple(types.shape) != (n,)):
+            raise ValueError("types must be an int32 tensor with one entry per atom")
         self.box, self.skin, self.natoms = b, skin, n
         check(lib.dp_build_nlist(self.model.h, n, _ptr(coords), _ptr(types), bp, skin, ctypes.byref(self.h),
                                  _stream()))
@@ -148,16 +154,22 @@ def descriptor(model, nlist, coords, mode=COMPRESSED, precision=FP64):
 
 
 def nve_run(model, nlist, x, v, box, mass, dt, nsteps, rebuild_every=10, skin=2.0, mode=COMPRESSED,
-            precision=FP64, thermo=True):
-    """Velocity-Verlet NVE in place on x, v (float64 device tensors).
+            precision=FP64, thermo=True, types=None):
+    """Velocity-Verlet NVE in place on x, v (float64 device tensors).  mass:
+    one number per type (a single number for a one-type model); types: int32
+    device tensor (None: all type 0).
     Returns the thermo tensor (nsteps+1, 2): potential and kinetic energy."""
     n = x.shape[0]
     _f64(x, (n, 3))
     _f64(v, (n, 3))
     th = torch.empty((nsteps + 1, 2), dtype=torch.float64, device=x.device) if thermo else None
     _, bp = _box(box)
-    check(lib.dp_nve_run(model.h, ctypes.byref(nlist.h), n, _ptr(x), _ptr(v), None, bp, mass, dt, nsteps,
-                         rebuild_every, skin, mode, precision, _ptr(th), _stream()))
+    m = np.ascontiguousarray(np.atleast_1d(np.asarray(mass, dtype=np.float64)))
+    if m.size != max(1, model.cfg.get("ntypes", 1)):
+        raise ValueError("one mass per type expected")
+    check(lib.dp_nve_run(model.h, ctypes.byref(nlist.h), n, _ptr(x), _ptr(v), _ptr(types), bp,
+                         m.ctypes.data_as(ctypes.c_void_p), dt, nsteps, rebuild_every, skin, mode, precision,
+                         _ptr(th), _stream()))
     nlist.box = None if box is None else np.asarray(box, dtype=np.float64).reshape(9)
     nlist.natoms = n
     return th

@@ -113,13 +113,21 @@ void free_fit(FitWeights &w)
     w = FitWeights{};
 }
 
-size_t expected_params(const dp_model_config &c)
+size_t emb_params(const dp_model_config &c)
 {
     size_t d1 = c.emb[0], d2 = c.emb[1], d3 = c.emb[2];
-    size_t f1 = c.fit[0], f2 = c.fit[1], f3 = c.fit[2];
-    size_t nD = (size_t)c.m_lt * d3;
-    return d1 + d1 + d1 * d2 + d2 + d2 * d3 + d3 + nD * f1 + f1 + f1 * f2 + f2 + f2 * f3 + f3 + f3 + 1;
+    return d1 + d1 + d1 * d2 + d2 + d2 * d3 + d3;
 }
+
+size_t fit_params(const dp_model_config &c)
+{
+    size_t f1 = c.fit[0], f2 = c.fit[1], f3 = c.fit[2];
+    size_t nD = (size_t)c.m_lt * c.emb[2];
+    return nD * f1 + f1 + f1 * f2 + f2 + f2 * f3 + f3 + f3 + 1;
+}
+
+// ntypes embedding nets, then ntypes fitting nets
+size_t expected_params(const dp_model_config &c) { return (size_t)c.ntypes * (emb_params(c) + fit_params(c)); }
 
 bool box_ok(const double *box, double L[3])
 {
@@ -136,7 +144,8 @@ bool box_ok(const double *box, double L[3])
 void free_nlist_arrays(dp_nlist *nl)
 {
     void *p[] = {nl->cell_cnt, nl->cell_atoms, nl->wpos, nl->wrap, nl->cnt, nl->nei, nl->shift,
-                 nl->dist, nl->rev, nl->pg, nl->flags, nl->ws, nl->ws_plain, nl->force_tmp, nl->scal};
+                 nl->dist, nl->rev, nl->pg, nl->flags, nl->ws, nl->ws_plain, nl->force_tmp, nl->scal,
+                 nl->type, nl->tcnt, nl->row, nl->ratom, nl->tblk};
     for (void *q : p)
         if (q) (void)hipFree(q);
 }
@@ -145,7 +154,7 @@ void free_nlist_arrays(dp_nlist *nl)
 dp_status prepare_nlist(const dp_model *m, int natoms, const double *box, double skin, dp_nlist **inout)
 {
     if (natoms <= 0) return fail(DP_ERR_ARG, "natoms must be positive");
-    if (natoms >= (1 << 25)) return fail(DP_ERR_UNSUPPORTED, "at most 2^25 - 1 atoms");
+    if (natoms >= (1 << 24)) return fail(DP_ERR_UNSUPPORTED, "at most 2^24 - 1 atoms");
     if (!(skin >= 0.0) || !std::isfinite(skin)) return fail(DP_ERR_ARG, "skin must be >= 0");
     dp_nlist *nl = *inout;
     bool fresh = nl == nullptr;
@@ -203,6 +212,9 @@ dp_status prepare_nlist(const dp_model *m, int natoms, const double *box, double
     if (cap < 128) cap = 128;
     if (cap > kCapMax) cap = kCapMax;
     bool grow = natoms > nl->alloc_atoms || cap > nl->cap;
+    const int T = m->cfg.ntypes;
+    // a list serves models of one type count; a change reallocates the type arrays
+    bool retype = T != nl->ntypes;
     if (grow) {
         int alloc = natoms > nl->alloc_atoms ? natoms : nl->alloc_atoms;
         int capn = cap > nl->cap ? cap : nl->cap;
@@ -220,6 +232,21 @@ dp_status prepare_nlist(const dp_model *m, int natoms, const double *box, double
         DP_HIP(hipMalloc(&nl->force_tmp, sizeof(double) * 3 * (size_t)alloc));
         nl->alloc_atoms = alloc;
         nl->cap = capn;
+    }
+    if (grow || retype) {
+        void *q[] = {nl->type, nl->tcnt, nl->row, nl->ratom, nl->tblk};
+        for (void *v : q)
+            if (v) DP_HIP(hipFree(v));
+        nl->type = nl->tcnt = nl->row = nl->ratom = nl->tblk = nullptr;
+        nl->ntypes = T;
+        if (T > 1) {
+            size_t A = (size_t)nl->alloc_atoms;
+            DP_HIP(hipMalloc(&nl->type, sizeof(int) * A));
+            DP_HIP(hipMalloc(&nl->tcnt, sizeof(int) * A * kMaxTypes));
+            DP_HIP(hipMalloc(&nl->row, sizeof(int) * A));
+            DP_HIP(hipMalloc(&nl->ratom, sizeof(int) * (size_t)fit_rows((long)A, T)));
+            DP_HIP(hipMalloc(&nl->tblk, sizeof(int) * ((size_t)div_up((long)A, 256) + 1) * kMaxTypes));
+        }
     }
     nl->cap = cap > nl->cap ? cap : nl->cap;
     if (!nl->flags) {
@@ -243,7 +270,7 @@ dp_status read_flags(dp_nlist *nl, int *f, hipStream_t st)
 
 dp_status check_build_flags(const int *f)
 {
-    if (f[kFlagBadType]) return fail(DP_ERR_UNSUPPORTED, "atom types other than 0 (one element only)");
+    if (f[kFlagBadType]) return fail(DP_ERR_ARG, "an atom type lies outside [0, ntypes)");
     if (f[kFlagCapOverflow])
         return fail(DP_ERR_CAPACITY, "an atom has more skin candidates than the list capacity "
                                      "(or coordinates lie more than 60 boxes away)");
@@ -259,7 +286,20 @@ dp_status check_compute_args(const dp_model *m, const dp_nlist *nl, int natoms, 
     if (mode < DP_COMPRESSED || mode > DP_FUSED) return fail(DP_ERR_ARG, "unknown mode");
     if (precision < DP_FP64 || precision > DP_MIXED_BF16) return fail(DP_ERR_ARG, "unknown precision");
     if (mode != DP_PLAIN && !m->tab64) return fail(DP_ERR_STATE, "dp_tabulate has not run");
+    if (nl->ntypes != m->cfg.ntypes) return fail(DP_ERR_ARG, "the list was built for a model of another type count");
+    if (m->cfg.ntypes > 1 && (mode == DP_PLAIN || mode == DP_TAB_UNFUSED))
+        return fail(DP_ERR_UNSUPPORTED, "several atom types need a fused mode (0, 3 or 4)");
     return DP_OK;
+}
+
+// The list's build at coordinates x: types first (several types group the
+// candidates by them), then the candidates and reverse slots.
+dp_status build_all(const dp_model *m, dp_nlist *nl, const double *x, const int *types, hipStream_t st)
+{
+    launch_fill_zero_int(nl->flags, kNumFlags, st);
+    dp_status s = build_type_layout(nl, types, st);
+    if (s != DP_OK) return s;
+    return launch_build_nlist(m, nl, x, types, false, st);
 }
 
 }  // namespace
@@ -273,7 +313,15 @@ dp_status dp_model_create(const dp_model_config *cfg, const double *params_h, si
 {
     if (!cfg || !params_h || !out) return fail(DP_ERR_ARG, "NULL argument");
     const dp_model_config &c = *cfg;
-    if (c.ntypes != 1) return fail(DP_ERR_UNSUPPORTED, "ntypes must be 1");
+    if (c.ntypes < 1 || c.ntypes > kMaxTypes) return fail(DP_ERR_UNSUPPORTED, "ntypes must be in [1, 4]");
+    if (c.ntypes > 1) {
+        int sum = 0;
+        for (int t = 0; t < c.ntypes; t++) {
+            if (c.sel_t[t] < 1) return fail(DP_ERR_ARG, "each sel_t must be >= 1");
+            sum += c.sel_t[t];
+        }
+        if (sum != c.sel) return fail(DP_ERR_ARG, "sel must equal the sum of sel_t");
+    }
     if (!(c.rcut > 0) || !(c.rcut_smth >= 0) || !(c.rcut_smth < c.rcut))
         return fail(DP_ERR_ARG, "need 0 <= rcut_smth < rcut");
     // the kernels keep up to sel neighbors per atom in LDS (64 KB per block)
@@ -298,41 +346,49 @@ dp_status dp_model_create(const dp_model_config *cfg, const double *params_h, si
     m->f1 = c.fit[0];
     m->f2 = c.fit[1];
     m->f3 = c.fit[2];
-    size_t nemb = (size_t)m->d1 * 2 + (size_t)m->d1 * m->d2 + m->d2 + (size_t)m->d2 * m->d3 + m->d3;
-    const double *p = params_h + nemb;
+    const int T = c.ntypes;
+    m->ntypes = T;
+    size_t nemb = emb_params(c), nfit = fit_params(c);
     int F = m->f1, P = kFitPad;
-    const double *V1 = p, *c1 = V1 + (size_t)kDdim * F, *V2 = c1 + F, *c2 = V2 + (size_t)F * F, *V3 = c2 + F,
-                 *c3 = V3 + (size_t)F * F, *w4 = c3 + F, *b4 = w4 + F;
+    // per center type: the GEMM operands (each matrix's copies back to back) and the vectors
     std::vector<double> mats[6];
-    mats[0].assign((size_t)kDdim * P, 0.0);   // V1  [2048][256]
-    mats[1].assign((size_t)P * kDdim, 0.0);   // V1t [256][2048]
-    for (int a = 0; a < kDdim; a++)
-        for (int o = 0; o < F; o++) {
-            mats[0][(size_t)a * P + o] = V1[(size_t)a * F + o];
-            mats[1][(size_t)o * kDdim + a] = V1[(size_t)a * F + o];
-        }
-    const double *Vs[2] = {V2, V3};
-    for (int k = 0; k < 2; k++) {
-        mats[2 + 2 * k].assign((size_t)P * P, 0.0);
-        mats[3 + 2 * k].assign((size_t)P * P, 0.0);
-        for (int a = 0; a < F; a++)
+    mats[0].assign((size_t)T * kDdim * P, 0.0);   // V1  [2048][256] per type
+    mats[1].assign((size_t)T * P * kDdim, 0.0);   // V1t [256][2048] per type
+    for (int k = 2; k < 6; k++) mats[k].assign((size_t)T * P * P, 0.0);
+    std::vector<double> fb((size_t)T * kFitB, 0.0);
+    for (int t = 0; t < T; t++) {
+        const double *p = params_h + (size_t)T * nemb + (size_t)t * nfit;
+        const double *V1 = p, *c1 = V1 + (size_t)kDdim * F, *V2 = c1 + F, *c2 = V2 + (size_t)F * F, *V3 = c2 + F,
+                     *c3 = V3 + (size_t)F * F, *w4 = c3 + F, *b4 = w4 + F;
+        double *M0 = mats[0].data() + (size_t)t * kDdim * P, *M1 = mats[1].data() + (size_t)t * P * kDdim;
+        for (int a = 0; a < kDdim; a++)
             for (int o = 0; o < F; o++) {
-                mats[2 + 2 * k][(size_t)a * P + o] = Vs[k][(size_t)a * F + o];
-                mats[3 + 2 * k][(size_t)o * P + a] = Vs[k][(size_t)a * F + o];
+                M0[(size_t)a * P + o] = V1[(size_t)a * F + o];
+                M1[(size_t)o * kDdim + a] = V1[(size_t)a * F + o];
             }
+        const double *Vs[2] = {V2, V3};
+        for (int k = 0; k < 2; k++) {
+            double *Ma = mats[2 + 2 * k].data() + (size_t)t * P * P, *Mb = mats[3 + 2 * k].data() + (size_t)t * P * P;
+            for (int a = 0; a < F; a++)
+                for (int o = 0; o < F; o++) {
+                    Ma[(size_t)a * P + o] = Vs[k][(size_t)a * F + o];
+                    Mb[(size_t)o * P + a] = Vs[k][(size_t)a * F + o];
+                }
+        }
+        double *f = fb.data() + (size_t)t * kFitB;
+        for (int o = 0; o < F; o++) {
+            f[o] = c1[o];
+            f[P + o] = c2[o];
+            f[2 * P + o] = c3[o];
+            f[3 * P + o] = w4[o];
+        }
+        f[4 * P] = b4[0];
+        m->b4[t] = b4[0];
     }
-    std::vector<double> fb(4 * P + 1, 0.0);
-    for (int o = 0; o < F; o++) {
-        fb[o] = c1[o];
-        fb[P + o] = c2[o];
-        fb[2 * P + o] = c3[o];
-        fb[3 * P + o] = w4[o];
-    }
-    fb[4 * P] = b4[0];
-    m->b4 = b4[0];
     std::vector<float> fbf(fb.begin(), fb.end());
-    std::vector<double> emb(params_h, params_h + nemb);
-    // embedding weights in the plain path's GEMM layouts (d1 = 32, d2 = 64, d3 = 128)
+    std::vector<double> emb(params_h, params_h + (size_t)T * nemb);
+    // embedding weights in the plain path's GEMM layouts (d1 = 32, d2 = 64, d3 = 128;
+    // one type: the plain modes serve one-type models only)
     const double *W0 = params_h, *b0 = W0 + 32, *W1 = b0 + 32, *b1 = W1 + 32 * 64, *W2 = b1 + 64,
                  *b2 = W2 + 64 * 128;
     std::vector<double> eg(64 * 32 + 128 * 64 + 64 * 128 + 64 * 64 + 32 + 32 + 64 + 128, 0.0);
@@ -412,9 +468,10 @@ dp_status dp_tabulate(dp_model *m, double s_max, double stride, double tail_max,
     m->tab.h_tail = n_tail ? tail_stride : stride;
     m->tab.tail_max = n_tail ? tail_max : s_max;
     int n = n_fine + n_tail;
-    DP_HIP(hipMalloc(&m->tab64, sizeof(double) * (size_t)n * kM * 6));
-    DP_HIP(hipMalloc(&m->tab32, sizeof(float) * (size_t)n * kM * 8));
-    DP_HIP(hipMalloc(&m->nodes, sizeof(double) * (size_t)(n + 1) * kM * 3));
+    size_t T = (size_t)m->ntypes;
+    DP_HIP(hipMalloc(&m->tab64, sizeof(double) * T * n * kM * 6));
+    DP_HIP(hipMalloc(&m->tab32, sizeof(float) * T * n * kM * 8));
+    DP_HIP(hipMalloc(&m->nodes, sizeof(double) * T * (n + 1) * kM * 3));
     dp_status s = launch_tabulate(m, (hipStream_t)stream);
     if (s != DP_OK) return s;
     return step_check("tabulate", (hipStream_t)stream);
@@ -441,7 +498,7 @@ dp_status dp_table_download(dp_model *m, double *coef_h, int *n_int)
     if (n_int) *n_int = n;
     if (coef_h) {
         DP_HIP(hipDeviceSynchronize());
-        DP_HIP(hipMemcpy(coef_h, m->tab64, sizeof(double) * (size_t)n * kM * 6, hipMemcpyDeviceToHost));
+        DP_HIP(hipMemcpy(coef_h, m->tab64, sizeof(double) * (size_t)m->ntypes * n * kM * 6, hipMemcpyDeviceToHost));
     }
     return DP_OK;
 }
@@ -455,7 +512,7 @@ dp_status dp_build_nlist(dp_model *m, int natoms, const double *coords_d, const 
         dp_status s = prepare_nlist(m, natoms, box_h, skin, inout);
         if (s != DP_OK) return s;
         dp_nlist *nl = *inout;
-        s = launch_build_nlist(m, nl, coords_d, types_d, true, st);
+        s = build_all(m, nl, coords_d, types_d, st);
         if (s != DP_OK) return s;
         if ((s = step_check("build_nlist", st)) != DP_OK) return s;
         int f[kNumFlags];
@@ -561,35 +618,45 @@ dp_status dp_nlist_stats(dp_nlist *nl, int *max_nei, int *n_sel_overflow, int *n
 }
 
 dp_status dp_nve_run(dp_model *m, dp_nlist **nlp, int natoms, double *x, double *v, const int *types,
-                     const double *box_h, double mass, double dt_fs, int nsteps, int rebuild_every, double skin,
-                     int mode, int precision, double *thermo, void *stream)
+                     const double *box_h, const double *mass_h, double dt_fs, int nsteps, int rebuild_every,
+                     double skin, int mode, int precision, double *thermo, void *stream)
 {
-    if (!m || !nlp || !x || !v) return fail(DP_ERR_ARG, "NULL argument");
-    if (!(mass > 0) || !(dt_fs > 0) || nsteps < 0 || rebuild_every < 1)
-        return fail(DP_ERR_ARG, "need mass > 0, dt > 0, nsteps >= 0, rebuild_every >= 1");
+    if (!m || !nlp || !x || !v || !mass_h) return fail(DP_ERR_ARG, "NULL argument");
+    const int T = m->cfg.ntypes;
+    for (int t = 0; t < T; t++)
+        if (!(mass_h[t] > 0) || !std::isfinite(mass_h[t])) return fail(DP_ERR_ARG, "need masses > 0");
+    if (!(dt_fs > 0) || nsteps < 0 || rebuild_every < 1)
+        return fail(DP_ERR_ARG, "need dt > 0, nsteps >= 0, rebuild_every >= 1");
     hipStream_t st = (hipStream_t)stream;
     dp_status s = prepare_nlist(m, natoms, box_h, skin, nlp);
     if (s != DP_OK) return s;
     dp_nlist *nl = *nlp;
     if ((s = check_compute_args(m, nl, natoms, x, mode, precision)) != DP_OK) return s;
-    if ((s = launch_build_nlist(m, nl, x, types, true, st)) != DP_OK) return s;
+    if ((s = build_all(m, nl, x, types, st)) != DP_OK) return s;
     if ((s = step_check("build_nlist", st)) != DP_OK) return s;
+    // rebuilds inside the run reuse the list's copy of the types
+    const int *tl = T > 1 ? nl->type : types;
+    const int *tk = T > 1 ? nl->type : nullptr;   // per-atom type of the Verlet kernels
     double *F = nl->force_tmp, *E = nl->scal, *part = nl->scal + 256;
-    double kick = 0.5 * dt_fs * acc_unit() / mass, kef = 0.5 * mass * ke_unit();
+    TypeScalars kick, kef;
+    for (int t = 0; t < T; t++) {
+        kick.v[t] = 0.5 * dt_fs * acc_unit() / mass_h[t];
+        kef.v[t] = 0.5 * mass_h[t] * ke_unit();
+    }
     s = compute_common(m, nl, natoms, x, mode, precision, E, F, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, st);
     if (s != DP_OK) return s;
-    if (thermo) launch_thermo(v, E, natoms, kef, thermo, part, st);
+    if (thermo) launch_thermo(v, E, natoms, tk, kef, thermo, part, st);
     for (int step = 1; step <= nsteps; step++) {
-        launch_verlet_kick_drift(x, v, F, natoms, kick, dt_fs, st);
+        launch_verlet_kick_drift(x, v, F, natoms, tk, kick, dt_fs, st);
         if (step % rebuild_every == 0) {
-            DP_TIMED("nlist", st, s = launch_build_nlist(m, nl, x, types, false, st));
+            DP_TIMED("nlist", st, s = launch_build_nlist(m, nl, x, tl, false, st));
             if (s != DP_OK) return s;
             if ((s = step_check("build_nlist", st)) != DP_OK) return s;
         }
         s = compute_common(m, nl, natoms, x, mode, precision, E, F, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, st);
         if (s != DP_OK) return s;
-        launch_verlet_kick(v, F, natoms, kick, st);
-        if (thermo) launch_thermo(v, E, natoms, kef, thermo + 2 * step, part, st);
+        launch_verlet_kick(v, F, natoms, tk, kick, st);
+        if (thermo) launch_thermo(v, E, natoms, tk, kef, thermo + 2 * step, part, st);
         if ((s = step_check("verlet", st)) != DP_OK) return s;
     }
     int f[kNumFlags];
@@ -602,8 +669,9 @@ dp_status dp_footprint_bytes(const dp_model *m, int natoms, size_t *bytes)
     if (!m || natoms < 0 || !bytes) return fail(DP_ERR_ARG, "bad argument");
     // candidates (index, shift, distance, reverse slot, pair gradient), positions, boxes, counts
     size_t per = (size_t)kCapMax * (4 + 4 + 4 + 2 + 24) + 3 * 8 + 3 * 8 + 4 * 4 + 3 * 8;
-    size_t ws = std::max(ws_bytes_for_atoms(natoms, DP_FP64, m->cfg.sel),
-                         ws_bytes_for_atoms(natoms, DP_MIXED_BF16, m->cfg.sel));
+    size_t ws = std::max(ws_bytes_for_atoms(natoms, DP_FP64, m->cfg.sel, m->cfg.ntypes),
+                         ws_bytes_for_atoms(natoms, DP_MIXED_BF16, m->cfg.sel, m->cfg.ntypes));
+    if (m->cfg.ntypes > 1) per += 4 * (2 + kMaxTypes) + 4;   // type, row, per-type counts, row map
     *bytes = per * (size_t)natoms + ws;
     return DP_OK;
 }
@@ -611,7 +679,8 @@ dp_status dp_footprint_bytes(const dp_model *m, int natoms, size_t *bytes)
 dp_status dp_batch_create(dp_model *m, int max_atoms, int max_requests, double skin, dp_batch **out)
 {
     if (!m || !out || max_atoms < 1 || max_requests < 1 || !(skin >= 0)) return fail(DP_ERR_ARG, "bad argument");
-    if (max_atoms >= (1 << 25)) return fail(DP_ERR_UNSUPPORTED, "at most 2^25 - 1 atoms");
+    if (max_atoms >= (1 << 24)) return fail(DP_ERR_UNSUPPORTED, "at most 2^24 - 1 atoms");
+    if (m->cfg.ntypes != 1) return fail(DP_ERR_UNSUPPORTED, "batches hold one-type models only");
     dp_batch *b = new dp_batch();
     b->max_atoms = max_atoms;
     b->max_req = max_requests;
@@ -670,6 +739,7 @@ dp_status dp_batch_compute(dp_model *m, dp_batch *b, int nreq, const dp_request 
                            double *atom_energy_d, void *stream)
 {
     if (!m || !b || !reqs || !coords_d || nreq < 1) return fail(DP_ERR_ARG, "bad argument");
+    if (m->cfg.ntypes != 1) return fail(DP_ERR_UNSUPPORTED, "batches hold one-type models only");
     if (nreq > b->max_req) return fail(DP_ERR_CAPACITY, "more requests than the batch was created for");
     if (!m->tab64) return fail(DP_ERR_STATE, "dp_tabulate has not run");
     if (precision < DP_FP64 || precision > DP_MIXED_BF16) return fail(DP_ERR_ARG, "unknown precision");

@@ -94,14 +94,35 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
     const dp_model *m = a.m;
     int n = a.natoms;
     dp_status s = DP_OK;
+    // vectors of type 0; a row group of type t reads them t * kFitB further
     const TR *c1 = fb, *c2 = fb + kFitPad, *c3 = fb + 2 * kFitPad, *w4 = fb + 3 * kFitPad;
     Epi e{};
     const int ks = k_split(a.precision);   // operand K multiplier (BF16 split)
     // GEMM rows: the live atoms rounded up to a whole 128-row tile (rows past
-    // n hold stale finite values and their outputs are never read); the
-    // buffers themselves are carved for the allocation's np rows.
-    const int mr = (int)round_up(n, kRowPad);
+    // n hold stale finite values and their outputs are never read); with
+    // several types, the type groups, each so rounded; the buffers
+    // themselves are carved for the allocation's np rows.
+    const dp_nlist *nl = a.nl;
+    const bool typed = nl->ntypes > 1;
+    const int mr = typed ? nl->rows : (int)round_up(n, kRowPad);
     (void)np;
+    // the weights of a tile's type group: one type's Bt (N x K) further per type
+    auto grouped = [&](Epi x, int N, int K) {
+        if (typed) {
+            x.ntr = nl->ntypes;
+            for (int t = 0; t <= kMaxTypes; t++) x.trow[t] = nl->trow[t];
+            x.bstride = (long)N * K;
+            x.vstride = kFitB;
+        }
+        return x;
+    };
+    RowTypes rt;
+    if (typed) {
+        rt.ntr = nl->ntypes;
+        for (int t = 0; t <= kMaxTypes; t++) rt.trow[t] = nl->trow[t];
+        rt.ratom = nl->ratom;
+    }
+    for (int t = 0; t < kMaxTypes; t++) rt.b4[t] = m->b4[t];
     bool fwd = a.phase != 2, bwd = a.need_forces && a.phase != 1;
     if (fwd) {
         if (PLAIN) {
@@ -116,29 +137,32 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
             if ((s = step_check("emb_fwd", st)) != DP_OK) return s;
         }
         if (a.T_out) launch_to_double<TR>((long)n * 4 * kM, (const TR *)w.T, a.T_out, st);
-        if (a.D_out) launch_op_to_double<TA>(n, kDdim, (const TA *)w.D, a.D_out, st);
+        if (a.D_out) launch_op_to_double<TA>(n, kDdim, (const TA *)w.D, typed ? nl->row : nullptr, a.D_out, st);
         // the fitting net's tanh: native, or tabulated in the FP32 and mixed modes when enabled
         const float *ttab = (a.precision != DP_FP64 && m->tanh_on) ? m->tanh_tab : nullptr;
         e = Epi{c1, nullptr, nullptr, nullptr, w.y1r, w.y1o, nullptr};
         e.tanh_tab = ttab;
+        e = grouped(e, kFitPad, ks * kDdim);
         DP_TIMED("fit_fwd1", st, launch_gemm<TA, TR>(EPI_T1, mr, kFitPad, ks * kDdim, (const TA *)w.D, (const TA *)fw.V1t, e, st));
         e = Epi{c2, w.y1r, nullptr, nullptr, w.y2r, w.y2o, w.t2r};
         e.tanh_tab = ttab;
+        e = grouped(e, kFitPad, ks * kFitPad);
         DP_TIMED("fit_fwd2", st, launch_gemm<TA, TR>(EPI_T2, mr, kFitPad, ks * kFitPad, (const TA *)w.y1o, (const TA *)fw.V2t, e, st));
         e = Epi{c3, nullptr, nullptr, nullptr, nullptr, nullptr, w.t3r};
         e.tanh_tab = ttab;
+        e = grouped(e, kFitPad, ks * kFitPad);
         DP_TIMED("fit_fwd3", st, launch_gemm<TA, TR>(EPI_T3, mr, kFitPad, ks * kFitPad, (const TA *)w.y2o, (const TA *)fw.V3t, e, st));
     }
     // E_i always; dz3 = w4 (1 - t3^2) when the backward follows
-    launch_energy<TA, TR>(n, (const TR *)w.y2r, (const TR *)w.t3r, w4, a.m->b4, w.e_atom,
+    launch_energy<TA, TR>(typed ? mr : n, (const TR *)w.y2r, (const TR *)w.t3r, w4, rt, w.e_atom,
                           bwd ? (TA *)w.dz3o : nullptr, st);
     if ((s = step_check("fitting_forward", st)) != DP_OK) return s;
     if (bwd) {
-        e = Epi{nullptr, nullptr, w4, w.t2r, w.dy2r, w.dz2o, nullptr};
+        e = grouped(Epi{nullptr, nullptr, w4, w.t2r, w.dy2r, w.dz2o, nullptr}, kFitPad, ks * kFitPad);
         DP_TIMED("fit_bwd3", st, launch_gemm<TA, TR>(EPI_BWD, mr, kFitPad, ks * kFitPad, (const TA *)w.dz3o, (const TA *)fw.V3, e, st));
-        e = Epi{nullptr, w.dy2r, nullptr, w.y1r, nullptr, w.dz1o, nullptr};
+        e = grouped(Epi{nullptr, w.dy2r, nullptr, w.y1r, nullptr, w.dz1o, nullptr}, kFitPad, ks * kFitPad);
         DP_TIMED("fit_bwd2", st, launch_gemm<TA, TR>(EPI_BWD, mr, kFitPad, ks * kFitPad, (const TA *)w.dz2o, (const TA *)fw.V2, e, st));
-        e = Epi{nullptr, nullptr, nullptr, nullptr, w.dDr, nullptr, nullptr};
+        e = grouped(Epi{nullptr, nullptr, nullptr, nullptr, w.dDr, nullptr, nullptr}, kDdim, ks * kFitPad);
         DP_TIMED("fit_bwd1", st, launch_gemm<TA, TR>(EPI_LIN, mr, kDdim, ks * kFitPad, (const TA *)w.dz1o, (const TA *)fw.V1, e, st));
         if (PLAIN) {
             DP_TIMED("dT", st, launch_dT<TR>(n, (const TR *)w.dDr, (const TR *)w.T, (TR *)w.dT, st));
@@ -171,14 +195,14 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
 
 }  // namespace
 
-size_t ws_bytes_for_atoms(int natoms, int precision, int sel)
+size_t ws_bytes_for_atoms(int natoms, int precision, int sel, int ntypes)
 {
-    return ws_bytes_for((int)round_up(natoms, kRowPad), precision, sel);
+    return ws_bytes_for((int)fit_rows(natoms, ntypes), precision, sel);
 }
 
 dp_status ensure_ws(dp_nlist *nl, int precision, int sel)
 {
-    int np = (int)round_up(nl->alloc_atoms, kRowPad);
+    int np = (int)fit_rows(nl->alloc_atoms, nl->ntypes);
     size_t need = ws_bytes_for(np, DP_FP64, sel);
     size_t need_bf = ws_bytes_for(np, DP_MIXED_BF16, sel);
     if (need_bf > need) need = need_bf;   // the largest of the three layouts
@@ -197,7 +221,7 @@ dp_status ensure_ws(dp_nlist *nl, int precision, int sel)
 
 dp_status run_compressed(const ComputeArgs &a, hipStream_t st)
 {
-    int np = (int)round_up(a.nl->alloc_atoms, kRowPad);
+    int np = (int)fit_rows(a.nl->alloc_atoms, a.nl->ntypes);
     WS w = carve(a.nl->ws, np, a.precision, a.m->cfg.sel);
     if (a.precision == DP_FP64) return run_t<double, double, false>(a, w, np, a.m->w64, a.m->fitb_d, st);
     if (a.precision == DP_FP32) return run_t<float, float, false>(a, w, np, a.m->w32, a.m->fitb_f, st);
@@ -206,7 +230,7 @@ dp_status run_compressed(const ComputeArgs &a, hipStream_t st)
 
 dp_status run_plain(const ComputeArgs &a, hipStream_t st)
 {
-    int np = (int)round_up(a.nl->alloc_atoms, kRowPad);
+    int np = (int)fit_rows(a.nl->alloc_atoms, a.nl->ntypes);
     WS w = carve(a.nl->ws, np, a.precision, a.m->cfg.sel);
     if (a.precision == DP_FP64) return run_t<double, double, true>(a, w, np, a.m->w64, a.m->fitb_d, st);
     if (a.precision == DP_FP32) return run_t<float, float, true>(a, w, np, a.m->w32, a.m->fitb_f, st);
@@ -221,29 +245,33 @@ constexpr double kAcc = 9.64853321e-3;
 constexpr double kKe = 103.642691;
 
 __global__ void k_kick_drift(double *__restrict__ x, double *__restrict__ v, const double *__restrict__ f,
-                             long n3, double kick, double dt)
+                             long n3, const int *__restrict__ type, TypeScalars kick, double dt)
 {
     long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (i >= n3) return;
-    double vi = v[i] + kick * f[i];
+    double k = kick.v[type ? type[i / 3] : 0];
+    double vi = v[i] + k * f[i];
     v[i] = vi;
     x[i] += dt * vi;
 }
 
-__global__ void k_kick(double *__restrict__ v, const double *__restrict__ f, long n3, double kick)
+__global__ void k_kick(double *__restrict__ v, const double *__restrict__ f, long n3, const int *__restrict__ type,
+                       TypeScalars kick)
 {
     long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (i < n3) v[i] += kick * f[i];
+    if (i < n3) v[i] += kick.v[type ? type[i / 3] : 0] * f[i];
 }
 
+// Per block a fixed slice of sum_i ke[type_i] |v_i|^2.
 __global__ void __launch_bounds__(256) k_vv_partial(long n3, const double *__restrict__ v,
+                                                    const int *__restrict__ type, TypeScalars ke,
                                                     double *__restrict__ part)
 {
     __shared__ double sh[256];
     long per = (n3 + gridDim.x - 1) / gridDim.x;
     long beg = blockIdx.x * per, end = min(n3, beg + per);
     double s = 0;
-    for (long i = beg + threadIdx.x; i < end; i += 256) s += v[i] * v[i];
+    for (long i = beg + threadIdx.x; i < end; i += 256) s += ke.v[type ? type[i / 3] : 0] * v[i] * v[i];
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
@@ -254,35 +282,35 @@ __global__ void __launch_bounds__(256) k_vv_partial(long n3, const double *__res
 }
 
 __global__ void k_thermo_final(int nblk, const double *__restrict__ part, const double *__restrict__ energy,
-                               double ke_factor, double *row)
+                               double *row)
 {
     if (threadIdx.x != 0) return;
     double s = 0;
     for (int b = 0; b < nblk; b++) s += part[b];
     row[0] = *energy;
-    row[1] = ke_factor * s;
+    row[1] = s;
 }
 
 }  // namespace
 
-void launch_verlet_kick_drift(double *x, double *v, const double *f, int n, double kick, double dt,
-                              hipStream_t st)
+void launch_verlet_kick_drift(double *x, double *v, const double *f, int n, const int *type, TypeScalars kick,
+                              double dt, hipStream_t st)
 {
     long n3 = 3L * n;
-    hipLaunchKernelGGL(k_kick_drift, dim3(div_up(n3, 256)), dim3(256), 0, st, x, v, f, n3, kick, dt);
+    hipLaunchKernelGGL(k_kick_drift, dim3(div_up(n3, 256)), dim3(256), 0, st, x, v, f, n3, type, kick, dt);
 }
 
-void launch_verlet_kick(double *v, const double *f, int n, double kick, hipStream_t st)
+void launch_verlet_kick(double *v, const double *f, int n, const int *type, TypeScalars kick, hipStream_t st)
 {
     long n3 = 3L * n;
-    hipLaunchKernelGGL(k_kick, dim3(div_up(n3, 256)), dim3(256), 0, st, v, f, n3, kick);
+    hipLaunchKernelGGL(k_kick, dim3(div_up(n3, 256)), dim3(256), 0, st, v, f, n3, type, kick);
 }
 
-void launch_thermo(const double *v, const double *energy, int n, double ke_factor, double *row, double *part,
-                   hipStream_t st)
+void launch_thermo(const double *v, const double *energy, int n, const int *type, TypeScalars ke, double *row,
+                   double *part, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_vv_partial, dim3(256), dim3(256), 0, st, 3L * n, v, part);
-    hipLaunchKernelGGL(k_thermo_final, dim3(1), dim3(64), 0, st, 256, part, energy, ke_factor, row);
+    hipLaunchKernelGGL(k_vv_partial, dim3(256), dim3(256), 0, st, 3L * n, v, type, ke, part);
+    hipLaunchKernelGGL(k_thermo_final, dim3(1), dim3(64), 0, st, 256, part, energy, row);
 }
 
 double acc_unit() { return kAcc; }

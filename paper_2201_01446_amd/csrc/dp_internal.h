@@ -19,6 +19,9 @@ constexpr int kDdim = kM * kMlt;     // 2048 descriptor entries per atom
 constexpr int kFitPad = 256;         // fitting widths padded to 256 (zero columns)
 constexpr int kCapMax = 1024;        // skin candidates per atom, upper bound
 constexpr int kRowPad = 128;         // atom rows of every GEMM operand padded to 128
+constexpr int kMaxTypes = DP_MAX_TYPES;
+// Per-type block of the fitting net's vectors: c1, c2, c3, w4 (kFitPad each), b4
+constexpr int kFitB = 4 * kFitPad + 64;
 
 // Device-side sticky counters of a neighbor list.
 enum Flag {
@@ -27,7 +30,7 @@ enum Flag {
     kFlagTableOob = 2,     // table look-ups past the last node
     kFlagCapOverflow = 3,  // atoms whose candidate list hit cap
     kFlagCellOverflow = 4, // atoms that did not fit their cell
-    kFlagBadType = 5,      // atoms with a type other than 0
+    kFlagBadType = 5,      // atoms with a type outside [0, ntypes)
     kNumFlags = 8
 };
 
@@ -37,7 +40,8 @@ struct TableInfo {
     int n_int() const { return n_fine + n_tail; }
 };
 
-// Fitting-net weights in one precision, widths padded to kFitPad.
+// Fitting-net weights in one precision, widths padded to kFitPad, one copy
+// per center type back to back (type t at t times one matrix's size).
 //   Vk  : [in][kFitPad] forward operands, Vkt : [kFitPad][in] transposed
 //   (backward operands), bias and output vector as float/double.
 struct FitWeights {
@@ -52,18 +56,19 @@ struct dp_model {
     int device = 0;
     int d1 = 0, d2 = 0, d3 = 0, f1 = 0, f2 = 0, f3 = 0;
     // parameters on the device
-    double *emb_d = nullptr;     // W0 b0 W1 b1 W2 b2, FP64, file layout
-    double *fitb_d = nullptr;    // c1 c2 c3 w4 (each kFitPad, zero padded) + b4, FP64
+    int ntypes = 1;
+    double *emb_d = nullptr;     // W0 b0 W1 b1 W2 b2 per neighbor type, FP64, file layout
+    double *fitb_d = nullptr;    // per center type (kFitB apart): c1 c2 c3 w4 (each kFitPad, zero padded), b4
     float *fitb_f = nullptr;     // same in FP32
-    double b4 = 0;               // output bias
+    double b4[dp::kMaxTypes] = {0, 0, 0, 0};   // output bias per center type
     dp::FitWeights w64, w32, wbf;   // double, float, bf16 GEMM operands
     void *embg64 = nullptr;      // embedding weights in GEMM layouts (plain path), FP64
     void *embg32 = nullptr;      // the same in FP32
     // table
     dp::TableInfo tab;
-    double *tab64 = nullptr;     // [n_int][M][6]
-    float *tab32 = nullptr;      // [n_int][M][8] (coefficients 0..5, two zero pads)
-    double *nodes = nullptr;     // scratch [n_int+1][M][3] of node values g, g', g''
+    double *tab64 = nullptr;     // [ntypes * n_int][M][6]: type t's table at interval t * n_int
+    float *tab32 = nullptr;      // [ntypes * n_int][M][8] (coefficients 0..5, two zero pads)
+    double *nodes = nullptr;     // scratch [ntypes][n_int+1][M][3] of node values g, g', g''
     // tanh of the fitting net in the FP32 and mixed modes: native, or the
     // second-order table [kTanhN][a0, a1, a2, 0] on [0, 8)
     float *tanh_tab = nullptr;
@@ -95,6 +100,18 @@ struct dp_nlist {
     short *rev = nullptr;    // [natoms * cap], slot of (i, -shift) in j's list, or -1
     void *pg = nullptr;      // [natoms * cap * 3] reals: dE_i/dr_ij per candidate slot
     int *flags = nullptr;    // [kNumFlags]
+    // several types: each atom's type, its candidates per type (the list is
+    // grouped by type), and the fitting net's row of each atom: rows are
+    // grouped by center type, group t at [trow[t], trow[t + 1]), each group
+    // padded to a whole GEMM tile; ratom maps a row back to its atom (-1: pad)
+    int ntypes = 1;
+    int *type = nullptr;     // [natoms]
+    int *tcnt = nullptr;     // [natoms * kMaxTypes]
+    int *row = nullptr;      // [natoms]
+    int *ratom = nullptr;    // [rows]
+    int *tblk = nullptr;     // scratch of the row assignment
+    int trow[dp::kMaxTypes + 1] = {0, 0, 0, 0, 0};
+    int rows = 0;            // trow[ntypes] when ntypes > 1
     // per-configuration scratch of dp_compute
     void *ws = nullptr;
     size_t ws_bytes = 0;
@@ -226,21 +243,37 @@ struct Epi {
     int resw = 0;      // EPI_EMB: width of the residual input
     int half = 0;      // EPI_FOLD
     const float *tanh_tab = nullptr;   // FP32 epilogues: tanh from this table (kTanhN x 4), or native
+    // rows grouped by type (several types): a tile whose first row lies in
+    // [trow[t], trow[t + 1]) takes Bt + t bstride and bias / resv + t vstride
+    int ntr = 0;
+    int trow[dp::kMaxTypes + 1] = {0, 0, 0, 0, 0};
+    long bstride = 0;
+    int vstride = 0;
 };
 template <typename TA, typename TR>
 void launch_gemm(int epi, int M, int N, int K, const TA *A, const TA *Bt, const Epi &e, hipStream_t st);
+// E_i and dz3 for rows [0, rows); several types: w4 and b4 of the row's
+// type group (Epi trow / vstride), E written to e_atom[ratom[row]] (pad rows
+// skipped); one type: e_atom[row].
+struct RowTypes {
+    int ntr = 0;
+    int trow[dp::kMaxTypes + 1] = {0, 0, 0, 0, 0};
+    double b4[kMaxTypes] = {0, 0, 0, 0};
+    const int *ratom = nullptr;
+};
 template <typename TA, typename TR>
-void launch_energy(int n, const TR *y2, const TR *t3, const TR *w4, double b4, double *e_atom, TA *dz3,
-                   hipStream_t st);
+void launch_energy(int rows, const TR *y2, const TR *t3, const TR *w4, const RowTypes &rt, double *e_atom,
+                   TA *dz3, hipStream_t st);
 template <typename TR>
 void launch_dT(int n, const TR *dD, const TR *T, TR *dT, hipStream_t st);
 void launch_reduce(int n, const double *e_atom, const double *w_atom, double *part, double *energy,
                    double *virial, hipStream_t st);
 template <typename T>
 void launch_to_double(long n, const T *a, double *b, hipStream_t st);
-// GEMM operand matrix (n rows, ncols logical columns) to FP64 (hi + lo for BF16)
+// GEMM operand matrix (n atoms, ncols logical columns) to FP64 (hi + lo for
+// BF16); atom i's row is row[i] (NULL: i)
 template <typename T>
-void launch_op_to_double(int n, int ncols, const T *a, double *b, hipStream_t st);
+void launch_op_to_double(int n, int ncols, const T *a, const int *row, double *b, hipStream_t st);
 // The per-neighbor rungs of the ablation (padded: rows up to sel included).
 void launch_emb_fwd_pn(const dp_model *m, const dp_nlist *nl, int n, const double *x, int precision, void *T,
                        void *D, void *rec, int *rcnt, bool padded, int *nnei, hipStream_t st);
@@ -279,19 +312,29 @@ template <typename real>
 dp_status plain_backward(const dp_model *m, dp_nlist *nl, int n, const void *dT, double *force, double *w_atom,
                          hipStream_t st, bool tabulated);
 dp_status ensure_ws(dp_nlist *nl, int precision, int sel);
+// GEMM rows a list of alloc_atoms atoms of ntypes types may need
+inline long fit_rows(long atoms, int ntypes) { return round_up(atoms, kRowPad) + (long)kRowPad * (ntypes - 1); }
+// Copies the types into the list, checks them, counts them per type and
+// assigns every atom its fitting-net row (synchronises once).
+dp_status build_type_layout(dp_nlist *nl, const int *types, hipStream_t st);
 // Reverse slots of the candidate lists of atoms [off, off + n) (after a build).
 void launch_reverse(dp_nlist *nl, int off, int n, hipStream_t st);
 // F_i = (F_i as written by the backward: sum_j dE_i/dr_ij) - sum over the
 // candidates j of i of dE_j/dr_ji, read from the pair gradients at the
 // reverse slot; deterministic (fixed order), no atomics.
 void launch_force_gather(const dp_nlist *nl, int n, int precision, double *force, hipStream_t st);
-size_t ws_bytes_for_atoms(int natoms, int precision, int sel);
+size_t ws_bytes_for_atoms(int natoms, int precision, int sel, int ntypes);
 dp_status run_compressed(const ComputeArgs &a, hipStream_t st);
 dp_status run_plain(const ComputeArgs &a, hipStream_t st);
-void launch_verlet_kick_drift(double *x, double *v, const double *f, int n, double kick, double dt,
-                              hipStream_t st);
-void launch_verlet_kick(double *v, const double *f, int n, double kick, hipStream_t st);
-void launch_thermo(const double *v, const double *energy, int n, double ke_factor, double *row,
+// Per-type kick factors 0.5 dt / m (A/fs per eV/A) and kinetic-energy
+// factors 0.5 m; type[i] of each atom (NULL: type 0).
+struct TypeScalars {
+    double v[kMaxTypes] = {0, 0, 0, 0};
+};
+void launch_verlet_kick_drift(double *x, double *v, const double *f, int n, const int *type, TypeScalars kick,
+                              double dt, hipStream_t st);
+void launch_verlet_kick(double *v, const double *f, int n, const int *type, TypeScalars kick, hipStream_t st);
+void launch_thermo(const double *v, const double *energy, int n, const int *type, TypeScalars ke, double *row,
                    double *part, hipStream_t st);
 double acc_unit();
 double ke_unit();

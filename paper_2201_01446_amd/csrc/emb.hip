@@ -190,8 +190,8 @@ __global__ void __launch_bounds__(256) k_emb_fwd(int natoms, EnvArgs A, const re
     p += kSegRound * 24 * sizeof(real);
     int *seg = reinterpret_cast<int *>(p);
     bool live = i < natoms;
-    int nn = 0, n_in = 0, oob = 0;
-    if (live) nn = build_env<real, ENV_FWD>(i, A, L, lane, n_in, oob);
+    int nn = 0, n_in = 0, over = 0, oob = 0;
+    if (live) nn = build_env<real, ENV_FWD>(i, A, L, lane, n_in, over, oob);
     __syncthreads();
     if (!live) return;
     int nseg = find_segments(L, nn, lane, seg);
@@ -272,7 +272,9 @@ __global__ void __launch_bounds__(256) k_emb_fwd(int natoms, EnvArgs A, const re
         T_out[(long)i * 4 * kM + k * kM + lane + 64] = T1[k];
     }
     wave_sync();
-    // D[a][b] = sum_k T[k][a] T[k][b], a < M<: lane owns b = lane, lane + 64
+    // D[a][b] = sum_k T[k][a] T[k][b], a < M<: lane owns b = lane, lane + 64;
+    // the row of the atom in the fitting net's operand (grouped by type)
+    const long drow = fit_row(A, i);
 #pragma unroll 4
     for (int a = 0; a < kMlt; a++) {
         real d0 = 0, d1 = 0;
@@ -282,13 +284,13 @@ __global__ void __launch_bounds__(256) k_emb_fwd(int natoms, EnvArgs A, const re
             d0 = fma(ta, T0[k], d0);
             d1 = fma(ta, T1[k], d1);
         }
-        store_op(D_out, i, a * kM + lane, kDdim, (double)d0);
-        store_op(D_out, i, a * kM + lane + 64, kDdim, (double)d1);
+        store_op(D_out, drow, a * kM + lane, kDdim, (double)d0);
+        store_op(D_out, drow, a * kM + lane + 64, kDdim, (double)d1);
     }
     // counters last: nothing in this kernel waits for these atomics
     if (nnei_out && lane == 0) nnei_out[i] = nn;
     if (nseg_out && lane == 0) nseg_out[i] = nseg;
-    record_flags<real>(A, lane, n_in, oob);
+    record_flags<real>(A, lane, n_in, over, oob);
 }
 
 // ------------------------------------------------------------- backward
@@ -328,7 +330,7 @@ __global__ void __launch_bounds__(256) k_emb_bwd(int natoms, EnvArgs A, const re
         constexpr int APG = kMlt / NG;
         int g = lane / GL, l = lane % GL;
         const real *Ti = T + (long)i * 4 * kM;
-        const real *dDi = dD + (long)i * kDdim;
+        const real *dDi = dD + fit_row(A, i) * kDdim;
         real dt[4][CPL], tc[4][CPL];
 #pragma unroll
         for (int c = 0; c < CPL; c++)

@@ -132,8 +132,8 @@ __global__ void __launch_bounds__(256) k_emb_fwd_pn(int natoms, EnvArgs A, const
     NbrLDS<real> L = carve<real>(base, A.sel, ENV_FWD);
     real *Tl = reinterpret_cast<real *>(base + nbr_lds_bytes<real>(A.sel, ENV_FWD));
     bool live = i < natoms;
-    int nn = 0, n_in = 0, oob = 0;
-    if (live) nn = build_env<real, ENV_FWD>(i, A, L, lane, n_in, oob);
+    int nn = 0, n_in = 0, over = 0, oob = 0;
+    if (live) nn = build_env<real, ENV_FWD>(i, A, L, lane, n_in, over, oob);
     __syncthreads();
     if (!live) return;
     int nrow = nn;
@@ -189,10 +189,10 @@ __global__ void __launch_bounds__(256) k_emb_fwd_pn(int natoms, EnvArgs A, const
         v = fma(Tl[kM + aa], Tl[kM + bb], v);
         v = fma(Tl[2 * kM + aa], Tl[2 * kM + bb], v);
         v = fma(Tl[3 * kM + aa], Tl[3 * kM + bb], v);
-        store_op(D_out, i, o, kDdim, (double)v);
+        store_op(D_out, fit_row(A, i), o, kDdim, (double)v);
     }
     if (nnei_out && lane == 0) nnei_out[i] = nn;
-    record_flags<real>(A, lane, n_in, oob);
+    record_flags<real>(A, lane, n_in, over, oob);
 }
 
 template <typename real, int CPL>
@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(256) k_emb_bwd_pn(int natoms, EnvArgs A, const
     // (group g takes the rows a of dD in [g APG, (g+1) APG); see emb.hip)
     constexpr int APG = kMlt / NG;
     const real *Ti = T + (long)i * 4 * kM;
-    const real *dDi = dD + (long)i * kDdim;
+    const real *dDi = dD + fit_row(A, i) * kDdim;
     real dt[4][CPL], tc[4][CPL];
 #pragma unroll
     for (int c = 0; c < CPL; c++)

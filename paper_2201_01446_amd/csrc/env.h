@@ -1,7 +1,11 @@
 // env.h -- the environment-matrix stage shared by the compressed and the
-// plain paths: filter the skin list to r < rcut, keep the sel nearest, and
-// form s = w(r)/r, R = s (1, x/r, y/r, z/r) (paper Eq. 1) and, for the
-// table, the interval of s and the offset from its left node (Sec. 3.2).
+// plain paths: filter the skin list to r < rcut, keep the sel nearest (with
+// several atom types: the sel_t nearest of each neighbor type), and form
+// s = w(r)/r, R = s (1, x/r, y/r, z/r) (paper Eq. 1) and, for the table, the
+// interval of s and the offset from its left node (Sec. 3.2).  Tables of the
+// types sit back to back, so a neighbor of type t in interval theta reads
+// global interval t n_int + theta; runs of equal global interval then never
+// mix types.
 #pragma once
 
 #include "dp_internal.h"
@@ -35,7 +39,17 @@ struct EnvArgs {
     // per candidate slot dE_i/dr_ij (3 reals; cap slots per atom): the forward
     // zeroes the slots it does not keep, the backward writes the kept ones
     void *pg;
+    // several atom types: per-type limits, the candidates of each type per
+    // atom (the list is grouped by type), one type's interval count
+    int ntypes;
+    int sel_t[kMaxTypes];
+    const int *tcnt;
+    int n_int;
+    // fitting-net row of each atom (NULL: the atom index)
+    const int *row;
 };
+
+__device__ inline long fit_row(const EnvArgs &A, int i) { return A.row ? A.row[i] : i; }
 
 // What a kernel keeps per neighbor in its LDS slice.
 enum EnvMode {
@@ -48,8 +62,8 @@ enum EnvMode {
 // Per-wave LDS slice (arrays of sel entries; V4 arrays first for alignment).
 template <typename real>
 struct NbrLDS {
-    V4<real> *R;   // R_j (ENV_FWD, ENV_PLAIN); holds r_ij during the scan
-    V4<real> *Dv;  // r_ij (ENV_BWD, ENV_PLAIN; in ENV_BWD also the scan's slot)
+    V4<real> *R;   // R_j (ENV_FWD, ENV_PLAIN); holds r_ij and the type during the scan
+    V4<real> *Dv;  // r_ij and the neighbor's type (ENV_BWD, ENV_PLAIN, ENV_BWDR)
     V4<real> *P;   // t, ds/dr, 1/r, s (ENV_PLAIN)
     real *t;       // offset of s_j from its interval's left node
     int *th;       // table interval (bit 30: s past the table end)
@@ -120,10 +134,12 @@ __device__ inline int table_interval(const EnvArgs &A, real s, int &th, real &t)
     return 1;
 }
 
-// Record of one compacted neighbor: r_ij and its candidate slot c (< 2^24,
-// exact in either precision's mantissa).
+// Record of one compacted neighbor: r_ij and its candidate slot c (< 2^24)
+// with the neighbor's type in bits 24..25 (an int carried in the bits of a
+// float, or exactly as a double).
 __device__ inline int record_slot(float w) { return __builtin_bit_cast(int, w); }
 __device__ inline int record_slot(double w) { return (int)w; }
+__device__ inline int slot_code(int c, int ty) { return c | (ty << 24); }
 template <typename real>
 __device__ inline void put_record(const EnvArgs &A, int i, int pos, double d0, double d1, double d2, int c)
 {
@@ -172,7 +188,10 @@ __device__ int finish_env(const EnvArgs &A, NbrLDS<real> L, int nn, int lane)
         env_geom<real>(A, d, rinv, s, sp);
         int th = 0;
         real t = 0;
-        if (TAB) oob += table_interval<real>(A, s, th, t);
+        if (TAB) {
+            oob += table_interval<real>(A, s, th, t);
+            th += (int)d.w * A.n_int;   // the neighbor type's table (d.w holds the type)
+        }
         if (MODE != ENV_BWD) L.R[k] = V4<real>{s, s * d.x * rinv, s * d.y * rinv, s * d.z * rinv};
         L.t[k] = t;
         L.th[k] = th;
@@ -184,29 +203,25 @@ __device__ int finish_env(const EnvArgs &A, NbrLDS<real> L, int nn, int lane)
     return oob;
 }
 
-// Neighbors of atom i within rcut, the sel nearest, into LDS; returns their
-// number (uniform over the wave).  *oob counts table look-ups past the end.
-template <typename real, int MODE, bool TAB = true>
-__device__ int build_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane, int &n_in_out,
-                         int &oob_out)
+// The candidates [c0, c0 + ct) of atom i (one neighbor type ty): those
+// within rcut, the lim nearest, go to LDS positions base, base + 1, ...
+// Returns how many lie within rcut.
+template <typename real, int MODE>
+__device__ int scan_candidates(int i, const EnvArgs &A, NbrLDS<real> L, int lane, int c0, int ct, int lim,
+                               int base, int ty, double xi0, double xi1, double xi2, double L0, double L1,
+                               double L2)
 {
-    int nc = A.cnt[i];
     const int *nei = A.nei + (long)i * A.cap;
     const int *shf = A.shift + (long)i * A.cap;
-    double xi0 = A.x[3 * i], xi1 = A.x[3 * i + 1], xi2 = A.x[3 * i + 2];
-    double L0 = A.L0, L1 = A.L1, L2 = A.L2;
-    if (A.atomL) {
-        L0 = A.atomL[3 * i];
-        L1 = A.atomL[3 * i + 1];
-        L2 = A.atomL[3 * i + 2];
-    }
+    const real rty = (real)ty;
     int n_in = 0;
-    for (int base = 0; base < nc; base += 64) {
-        int k = base + lane;
+    for (int b = 0; b < ct; b += 64) {
+        int k = c0 + b + lane;
+        bool live = b + lane < ct;
         bool in = false;
         double d0 = 0, d1 = 0, d2 = 0;
         int j = 0;
-        if (k < nc) {
+        if (live) {
             j = nei[k];
             int s = shf[k];
             d0 = (A.x[3 * j] - xi0) + s8(s, 0) * L0;
@@ -215,18 +230,19 @@ __device__ int build_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane, int 
             in = d0 * d0 + d1 * d1 + d2 * d2 < A.rc2;
         }
         unsigned long long mask = __ballot(in);
-        int pos = n_in + __popcll(mask & ((1ull << lane) - 1ull));
-        if (in && pos < A.sel) {
-            (MODE == ENV_BWD ? L.Dv : L.R)[pos] = V4<real>{(real)d0, (real)d1, (real)d2, (real)0};
+        int q = n_in + __popcll(mask & ((1ull << lane) - 1ull));
+        if (in && q < lim) {
+            int pos = base + q;
+            (MODE == ENV_BWD ? L.Dv : L.R)[pos] = V4<real>{(real)d0, (real)d1, (real)d2, rty};
             if (MODE != ENV_FWD) L.j[pos] = j;
-            if (MODE == ENV_FWD && A.rec) put_record<real>(A, i, pos, d0, d1, d2, k);
+            if (MODE == ENV_FWD && A.rec) put_record<real>(A, i, pos, d0, d1, d2, slot_code(k, ty));
         }
-        if (MODE == ENV_FWD && A.pg && k < nc && !in) zero_pg<real>(A, i, k);
+        if (MODE == ENV_FWD && A.pg && live && !in) zero_pg<real>(A, i, k);
         n_in += __popcll(mask);
     }
-    if (n_in > A.sel) {
-        // keep the sel nearest by (r^2, j, image); ranks are a permutation
-        for (int k = lane; k < nc; k += 64) {
+    if (n_in > lim) {
+        // keep the lim nearest by (r^2, j, image); ranks are a permutation
+        for (int k = c0 + lane; k < c0 + ct; k += 64) {
             int j = nei[k], s = shf[k];
             double d0 = (A.x[3 * j] - xi0) + s8(s, 0) * L0;
             double d1 = (A.x[3 * j + 1] - xi1) + s8(s, 8) * L1;
@@ -234,7 +250,7 @@ __device__ int build_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane, int 
             double r2 = d0 * d0 + d1 * d1 + d2 * d2;
             if (!(r2 < A.rc2)) continue;
             int rank = 0;
-            for (int q = 0; q < nc; q++) {
+            for (int q = c0; q < c0 + ct; q++) {
                 int jq = nei[q], sq = shf[q];
                 double e0 = (A.x[3 * jq] - xi0) + s8(sq, 0) * L0;
                 double e1 = (A.x[3 * jq + 1] - xi1) + s8(sq, 8) * L1;
@@ -244,22 +260,59 @@ __device__ int build_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane, int 
                 bool less = rq < r2 || (rq == r2 && (jq < j || (jq == j && sq < s)));
                 rank += less ? 1 : 0;
             }
-            if (rank < A.sel) {
-                (MODE == ENV_BWD ? L.Dv : L.R)[rank] = V4<real>{(real)d0, (real)d1, (real)d2, (real)0};
-                if (MODE != ENV_FWD) L.j[rank] = j;
-                if (MODE == ENV_FWD && A.rec) put_record<real>(A, i, rank, d0, d1, d2, k);
+            if (rank < lim) {
+                int pos = base + rank;
+                (MODE == ENV_BWD ? L.Dv : L.R)[pos] = V4<real>{(real)d0, (real)d1, (real)d2, rty};
+                if (MODE != ENV_FWD) L.j[pos] = j;
+                if (MODE == ENV_FWD && A.rec) put_record<real>(A, i, pos, d0, d1, d2, slot_code(k, ty));
             } else if (MODE == ENV_FWD && A.pg) {
-                zero_pg<real>(A, i, k);   // within rcut but beyond the sel nearest
+                zero_pg<real>(A, i, k);   // within rcut but beyond the lim nearest
             }
         }
     }
-    int nn = n_in < A.sel ? n_in : A.sel;
+    return n_in;
+}
+
+// Neighbors of atom i within rcut, the sel nearest (of each type the sel_t
+// nearest), into LDS, grouped by type; returns their number (uniform over
+// the wave).  n_in_out: neighbors within rcut; over_out: 1 when a limit cut
+// some off; oob_out: table look-ups past the end.
+template <typename real, int MODE, bool TAB = true>
+__device__ int build_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane, int &n_in_out, int &over_out,
+                         int &oob_out)
+{
+    int nc = A.cnt[i];
+    double xi0 = A.x[3 * i], xi1 = A.x[3 * i + 1], xi2 = A.x[3 * i + 2];
+    double L0 = A.L0, L1 = A.L1, L2 = A.L2;
+    if (A.atomL) {
+        L0 = A.atomL[3 * i];
+        L1 = A.atomL[3 * i + 1];
+        L2 = A.atomL[3 * i + 2];
+    }
+    int nn = 0, n_in = 0, over = 0;
+    if (A.ntypes <= 1) {
+        n_in = scan_candidates<real, MODE>(i, A, L, lane, 0, nc, A.sel, 0, 0, xi0, xi1, xi2, L0, L1, L2);
+        nn = n_in < A.sel ? n_in : A.sel;
+        over = n_in > A.sel;
+    } else {
+        int c0 = 0;
+        for (int ty = 0; ty < A.ntypes; ty++) {
+            int ct = A.tcnt[(long)i * kMaxTypes + ty];
+            int lim = A.sel_t[ty];
+            int m = scan_candidates<real, MODE>(i, A, L, lane, c0, ct, lim, nn, ty, xi0, xi1, xi2, L0, L1, L2);
+            nn += m < lim ? m : lim;
+            n_in += m;
+            over |= m > lim;
+            c0 += ct;
+        }
+    }
     if (MODE == ENV_FWD && A.rec && lane == 0) A.rcnt[i] = nn;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     oob_out = finish_env<real, MODE, TAB>(A, L, nn, lane);
     n_in_out = n_in;
+    over_out = over;
     return nn;
 }
 
@@ -272,8 +325,9 @@ __device__ int load_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane)
     const V4<real> *rec = reinterpret_cast<const V4<real> *>(A.rec) + (long)i * A.sel;
     for (int k = lane; k < nn; k += 64) {
         V4<real> r = rec[k];
-        L.Dv[k] = V4<real>{r.x, r.y, r.z, (real)0};
-        L.j[k] = record_slot(r.w);
+        int code = record_slot(r.w);
+        L.Dv[k] = V4<real>{r.x, r.y, r.z, (real)(code >> 24)};
+        L.j[k] = code & 0xFFFFFF;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -283,13 +337,13 @@ __device__ int load_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane)
 }
 
 template <typename real>
-__device__ inline void record_flags(const EnvArgs &A, int lane, int n_in, int oob)
+__device__ inline void record_flags(const EnvArgs &A, int lane, int n_in, int over, int oob)
 {
     // wave-wide sum of oob
     for (int off = 32; off > 0; off >>= 1) oob += __shfl_xor(oob, off);
     if (lane == 0) {
         atomicMax(&A.flags[kFlagMaxNei], n_in);
-        if (n_in > A.sel) atomicAdd(&A.flags[kFlagSelOverflow], 1);
+        if (over) atomicAdd(&A.flags[kFlagSelOverflow], 1);
         if (oob) atomicAdd(&A.flags[kFlagTableOob], oob);
     }
 }
@@ -350,6 +404,11 @@ inline EnvArgs make_env_args(const dp_model *m, const dp_nlist *nl, const double
     A.rec = nullptr;
     A.rcnt = nullptr;
     A.pg = nullptr;
+    A.ntypes = nl->ntypes;
+    for (int t = 0; t < kMaxTypes; t++) A.sel_t[t] = t < m->cfg.ntypes ? m->cfg.sel_t[t] : 0;
+    A.tcnt = nl->ntypes > 1 ? nl->tcnt : nullptr;
+    A.n_int = m->tab.n_int();
+    A.row = nl->ntypes > 1 ? nl->row : nullptr;
     return A;
 }
 

@@ -155,6 +155,10 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const TA *
     int row0 = (tile / ntn) * BM, col0 = (tile % ntn) * BN;
     int wr = wave >> 1, wc = wave & 1;
     int m = lane & 15, q = lane >> 4;
+    // rows grouped by atom type: the tile's group selects the weights
+    int ty = 0;
+    for (int g = 1; g < e.ntr; g++) ty += row0 >= e.trow[g] ? 1 : 0;
+    Bt += ty * e.bstride;
 
     const char *Ag = reinterpret_cast<const char *>(A) + (long)row0 * K * sizeof(TA);
     const char *Bg = reinterpret_cast<const char *>(Bt) + (long)col0 * K * sizeof(TA);
@@ -206,7 +210,8 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const TA *
     // row = wr*16TM + a*16 + r, where r = 4q + i for the FP32-accumulating
     // instructions and r = 4i + q for v_mfma_f64_16x16x4f64 (lane layouts
     // measured on gfx950)
-    const TR *bias = (const TR *)e.bias;
+    const TR *bias = e.bias ? (const TR *)e.bias + ty * e.vstride : nullptr;
+    const TR *resv = e.resv ? (const TR *)e.resv + ty * e.vstride : nullptr;
     constexpr bool kF64 = std::is_same<TA, double>::value;
 #pragma unroll
     for (int a = 0; a < TM; a++)
@@ -246,7 +251,7 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const TA *
                         store_op((TA *)e.out_o, gm, gn, e.half, (double)(dy * ((TR)1 - t * t)));
                     }
                 } else {
-                    TR dy = (e.resv ? ((const TR *)e.resv)[gn] : ((const TR *)e.res)[idx]) + v;
+                    TR dy = (resv ? resv[gn] : ((const TR *)e.res)[idx]) + v;
                     if (e.out_r) ((TR *)e.out_r)[idx] = dy;
                     TR t = ((const TR *)e.tt)[idx];
                     store_op((TA *)e.out_o, gm, gn, N, (double)(dy * ((TR)1 - t * t)));
@@ -254,15 +259,20 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const TA *
             }
 }
 
-// E_i = (y2 + t3) . w4 + b4 and dz3 = w4 (1 - t3^2): one wave per atom.
+// E_i = (y2 + t3) . w4 + b4 and dz3 = w4 (1 - t3^2): one wave per row.
+// Several types: w4 and b4 of the row's type group, E to the row's atom
+// (pad rows only get dz3, which nothing reads back).
 template <typename TA, typename TR>
-__global__ void __launch_bounds__(256) k_energy(int n, const TR *__restrict__ y2, const TR *__restrict__ t3,
-                                                const TR *__restrict__ w4, double b4,
+__global__ void __launch_bounds__(256) k_energy(int rows, const TR *__restrict__ y2, const TR *__restrict__ t3,
+                                                const TR *__restrict__ w4_all, RowTypes rt,
                                                 double *__restrict__ e_atom, TA *__restrict__ dz3)
 {
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int i = blockIdx.x * 4 + wave;
-    if (i >= n) return;
+    if (i >= rows) return;
+    int ty = 0;
+    for (int g = 1; g < rt.ntr; g++) ty += i >= rt.trow[g] ? 1 : 0;
+    const TR *w4 = w4_all + ty * kFitB;
     TR acc = 0;
     for (int c = lane; c < kFitPad; c += 64) {
         long idx = (long)i * kFitPad + c;
@@ -271,7 +281,8 @@ __global__ void __launch_bounds__(256) k_energy(int n, const TR *__restrict__ y2
         if (dz3) store_op(dz3, i, c, kFitPad, (double)(w4[c] * ((TR)1 - t * t)));
     }
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (lane == 0) e_atom[i] = (double)acc + b4;
+    int atom = rt.ratom ? rt.ratom[i] : i;
+    if (lane == 0 && atom >= 0) e_atom[atom] = (double)acc + rt.b4[ty];
 }
 
 // dT[k][c] = sum_{a<M<} dD[a][c] T[k][a] + [c<M<] sum_b dD[c][b] T[k][b]
@@ -376,16 +387,18 @@ __global__ void k_to_double<double>(long n, const double *__restrict__ a, double
 }
 
 template <typename T>
-__global__ void k_op_to_double(long n, int ncols, const T *__restrict__ a, double *__restrict__ b)
+__global__ void k_op_to_double(long n, int ncols, const T *__restrict__ a, const int *__restrict__ rowmap,
+                               double *__restrict__ b)
 {
     long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    long row = i / ncols;
+    long atom = i / ncols;
+    long row = rowmap ? rowmap[atom] : atom;
     int col = (int)(i % ncols);
     if constexpr (std::is_same<T, __bf16>::value)
         b[i] = (double)(float)a[row * 3 * ncols + col] + (double)(float)a[row * 3 * ncols + 2 * ncols + col];
     else
-        b[i] = (double)a[i];
+        b[i] = (double)a[row * ncols + col];
 }
 
 __global__ void k_fill_zero(double *p, long n)
@@ -433,14 +446,15 @@ template void launch_gemm<float, float>(int, int, int, int, const float *, const
 template void launch_gemm<__bf16, float>(int, int, int, int, const __bf16 *, const __bf16 *, const Epi &, hipStream_t);
 
 template <typename TA, typename TR>
-void launch_energy(int n, const TR *y2, const TR *t3, const TR *w4, double b4, double *e_atom, TA *dz3,
+void launch_energy(int rows, const TR *y2, const TR *t3, const TR *w4, const RowTypes &rt, double *e_atom, TA *dz3,
                    hipStream_t st)
 {
-    hipLaunchKernelGGL((k_energy<TA, TR>), dim3(div_up(n, 4)), dim3(256), 0, st, n, y2, t3, w4, b4, e_atom, dz3);
+    hipLaunchKernelGGL((k_energy<TA, TR>), dim3(div_up(rows, 4)), dim3(256), 0, st, rows, y2, t3, w4, rt, e_atom,
+                       dz3);
 }
-template void launch_energy<double, double>(int, const double *, const double *, const double *, double, double *, double *, hipStream_t);
-template void launch_energy<float, float>(int, const float *, const float *, const float *, double, double *, float *, hipStream_t);
-template void launch_energy<__bf16, float>(int, const float *, const float *, const float *, double, double *, __bf16 *, hipStream_t);
+template void launch_energy<double, double>(int, const double *, const double *, const double *, const RowTypes &, double *, double *, hipStream_t);
+template void launch_energy<float, float>(int, const float *, const float *, const float *, const RowTypes &, double *, float *, hipStream_t);
+template void launch_energy<__bf16, float>(int, const float *, const float *, const float *, const RowTypes &, double *, __bf16 *, hipStream_t);
 
 template <typename TR>
 void launch_dT(int n, const TR *dD, const TR *T, TR *dT, hipStream_t st)
@@ -467,14 +481,15 @@ template void launch_to_double<float>(long, const float *, double *, hipStream_t
 template void launch_to_double<__bf16>(long, const __bf16 *, double *, hipStream_t);
 
 template <typename T>
-void launch_op_to_double(int n, int ncols, const T *a, double *b, hipStream_t st)
+void launch_op_to_double(int n, int ncols, const T *a, const int *row, double *b, hipStream_t st)
 {
     long tot = (long)n * ncols;
-    if (tot > 0) hipLaunchKernelGGL((k_op_to_double<T>), dim3(div_up(tot, 256)), dim3(256), 0, st, tot, ncols, a, b);
+    if (tot > 0)
+        hipLaunchKernelGGL((k_op_to_double<T>), dim3(div_up(tot, 256)), dim3(256), 0, st, tot, ncols, a, row, b);
 }
-template void launch_op_to_double<double>(int, int, const double *, double *, hipStream_t);
-template void launch_op_to_double<float>(int, int, const float *, double *, hipStream_t);
-template void launch_op_to_double<__bf16>(int, int, const __bf16 *, double *, hipStream_t);
+template void launch_op_to_double<double>(int, int, const double *, const int *, double *, hipStream_t);
+template void launch_op_to_double<float>(int, int, const float *, const int *, double *, hipStream_t);
+template void launch_op_to_double<__bf16>(int, int, const __bf16 *, const int *, double *, hipStream_t);
 
 void launch_fill_zero(double *p, long n, hipStream_t st)
 {

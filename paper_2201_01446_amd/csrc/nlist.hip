@@ -7,6 +7,10 @@
 // rcut + skin, sorted by distance; the sort makes neighbors that fall into
 // the same table interval consecutive, which the fused kernels exploit.
 //
+// With several atom types the candidates are grouped by the neighbor's type
+// (nearest first within a type) and their number per type is kept, so that
+// the per-type limits and tables apply to contiguous runs.
+//
 // Periodic boxes: atoms are wrapped into the box and binned into a grid of
 // nc >= 1 cells per edge with edge >= (rcut + skin)/2.  An atom scans the
 // cell offsets -R..R (R <= 2) per axis; an offset that leaves the grid maps to
@@ -30,13 +34,15 @@ __device__ inline int pack_shift(int a, int b, int c)
     return (a & 0xFF) | ((b & 0xFF) << 8) | ((c & 0xFF) << 16);
 }
 
-// 64-bit sort key: distance (float bits; non-negative floats order like
-// unsigned integers), then atom index, then image code (5 values per axis).
-__device__ inline unsigned long long make_key(float r, int j, int code)
+// 64-bit sort key: type (2 bits), distance (31 bits: the bits of a
+// non-negative float, which order like unsigned integers), atom index (24
+// bits), image code (7 bits, 5 values per axis).
+__device__ inline unsigned long long make_key(int ty, float r, int j, int code)
 {
-    return ((unsigned long long)__float_as_uint(r) << 32) |
+    return ((unsigned long long)(unsigned)ty << 62) | ((unsigned long long)__float_as_uint(r) << 31) |
            ((unsigned long long)(unsigned)j << 7) | (unsigned)code;
 }
+__device__ inline int key_type(unsigned long long k) { return (int)(k >> 62); }
 
 __global__ void k_zero_int(int *p, long n)
 {
@@ -52,7 +58,7 @@ __global__ void k_bin(int n, const double *__restrict__ x, const int *__restrict
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    if (types && types[i] != 0) atomicAdd(&flags[kFlagBadType], 1);
+    if (types && types[i] != 0) atomicAdd(&flags[kFlagBadType], 1);   // one-type lists only
     double L[3] = {Lx, Ly, Lz};
     int nc[3] = {ncx, ncy, ncz};
     int k[3], c[3];
@@ -99,7 +105,7 @@ __device__ void bitonic_sort(unsigned long long *keys, int P)
 
 __device__ void finish_atom(int i, int cnt, int cap, unsigned long long *keys, const int *wrap,
                             int ki_packed, int *out_cnt, int *out_nei, int *out_shift, float *out_dist,
-                            int *flags, int joff)
+                            int *out_tcnt, int *flags, int joff)
 {
     int lane = threadIdx.x;
     if (cnt > cap) {
@@ -115,8 +121,8 @@ __device__ void finish_atom(int i, int cnt, int cap, unsigned long long *keys, c
         kiz = (int)(signed char)((ki_packed >> 16) & 0xFF);
     for (int t = lane; t < cnt; t += 64) {
         unsigned long long key = keys[t];
-        int lo = (int)(key & 0xFFFFFFFFu);
-        int j = (int)((unsigned)lo >> 7);
+        int lo = (int)(key & 0x7FFFFFFFu);
+        int j = lo >> 7;
         int code = lo & 127;
         int sx = code / 25 - 2, sy = (code / 5) % 5 - 2, sz = code % 5 - 2;
         int kj = wrap ? wrap[j] : 0;
@@ -124,7 +130,16 @@ __device__ void finish_atom(int i, int cnt, int cap, unsigned long long *keys, c
             kjz = (int)(signed char)((kj >> 16) & 0xFF);
         out_nei[(long)i * cap + t] = j + joff;
         out_shift[(long)i * cap + t] = pack_shift(sx + kix - kjx, sy + kiy - kjy, sz + kiz - kjz);
-        out_dist[(long)i * cap + t] = __uint_as_float((unsigned)(key >> 32));
+        out_dist[(long)i * cap + t] = __uint_as_float((unsigned)((key >> 31) & 0x7FFFFFFFu));
+    }
+    if (out_tcnt) {
+        int c[kMaxTypes] = {0, 0, 0, 0};
+        for (int b = 0; b < cnt; b += 64) {
+            int ty = b + lane < cnt ? key_type(keys[b + lane]) : -1;
+            for (int q = 0; q < kMaxTypes; q++) c[q] += __popcll(__ballot(ty == q));
+        }
+        if (lane == 0)
+            for (int q = 0; q < kMaxTypes; q++) out_tcnt[(long)i * kMaxTypes + q] = c[q];
     }
     if (lane == 0) out_cnt[i] = cnt;
 }
@@ -134,8 +149,9 @@ __global__ void __launch_bounds__(64) k_candidates_cells(
     int n, const double *__restrict__ wpos, const int *__restrict__ wrap, double Lx, double Ly,
     double Lz, int ncx, int ncy, int ncz, int Rx, int Ry, int Rz, int cellcap,
     const int *__restrict__ cell_cnt, const int *__restrict__ cell_atoms, double rcs2, int cap,
-    int *__restrict__ out_cnt, int *__restrict__ out_nei, int *__restrict__ out_shift,
-    float *__restrict__ out_dist, int *__restrict__ flags, int joff)
+    const int *__restrict__ types, int *__restrict__ out_cnt, int *__restrict__ out_nei,
+    int *__restrict__ out_shift, float *__restrict__ out_dist, int *__restrict__ out_tcnt,
+    int *__restrict__ flags, int joff)
 {
     HIP_DYNAMIC_SHARED(unsigned long long, keys)
     __shared__ int count;
@@ -169,21 +185,26 @@ __global__ void __launch_bounds__(64) k_candidates_cells(
             double r2 = d0 * d0 + d1 * d1 + d2 * d2;
             if (r2 < rcs2 && !(j == i && sx == 0 && sy == 0 && sz == 0)) {
                 int slot = atomicAdd(&count, 1);
-                if (slot < cap) keys[slot] = make_key((float)sqrt(r2), j, code);
+                if (slot < cap) keys[slot] = make_key(types ? types[j] : 0, (float)sqrt(r2), j, code);
             }
         }
     }
     __syncthreads();
-    finish_atom(i, count, cap, keys, wrap, wrap[i], out_cnt, out_nei, out_shift, out_dist, flags, joff);
+    finish_atom(i, count, cap, keys, wrap, wrap[i], out_cnt, out_nei, out_shift, out_dist, out_tcnt, flags,
+                joff);
 }
 
 // Open boundary: brute force over all atoms (for clusters of modest size).
+// check_types: one-type lists flag any type other than 0; key_types: the
+// types that group a several-type list (NULL: one type).
 __global__ void __launch_bounds__(64) k_candidates_open(int n, const double *__restrict__ x,
-                                                        const int *__restrict__ types, double rcs2,
+                                                        const int *__restrict__ check_types,
+                                                        const int *__restrict__ key_types, double rcs2,
                                                         int cap, int *__restrict__ out_cnt,
                                                         int *__restrict__ out_nei,
                                                         int *__restrict__ out_shift,
                                                         float *__restrict__ out_dist,
+                                                        int *__restrict__ out_tcnt,
                                                         int *__restrict__ flags, int joff)
 {
     HIP_DYNAMIC_SHARED(unsigned long long, keys)
@@ -193,7 +214,7 @@ __global__ void __launch_bounds__(64) k_candidates_open(int n, const double *__r
     int lane = threadIdx.x;
     if (lane == 0) {
         count = 0;
-        if (types && types[i] != 0) atomicAdd(&flags[kFlagBadType], 1);
+        if (check_types && check_types[i] != 0) atomicAdd(&flags[kFlagBadType], 1);
     }
     __syncthreads();
     double xi0 = x[3 * i], xi1 = x[3 * i + 1], xi2 = x[3 * i + 2];
@@ -203,11 +224,12 @@ __global__ void __launch_bounds__(64) k_candidates_open(int n, const double *__r
         double r2 = d0 * d0 + d1 * d1 + d2 * d2;
         if (r2 < rcs2) {
             int slot = atomicAdd(&count, 1);
-            if (slot < cap) keys[slot] = make_key((float)sqrt(r2), j, 62 /* image (0,0,0) */);
+            if (slot < cap)
+                keys[slot] = make_key(key_types ? key_types[j] : 0, (float)sqrt(r2), j, 62 /* image (0,0,0) */);
         }
     }
     __syncthreads();
-    finish_atom(i, count, cap, keys, nullptr, 0, out_cnt, out_nei, out_shift, out_dist, flags, joff);
+    finish_atom(i, count, cap, keys, nullptr, 0, out_cnt, out_nei, out_shift, out_dist, out_tcnt, flags, joff);
 }
 
 }  // namespace
@@ -227,16 +249,21 @@ dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, c
     while (cap2 < nl->cap) cap2 <<= 1;
     size_t lds = sizeof(unsigned long long) * cap2;
     (void)m;
+    // several types: the list's own copy (checked by build_type_layout) groups the candidates
+    const bool typed = nl->ntypes > 1;
+    const int *check = typed ? nullptr : types;
+    const int *ktypes = typed ? nl->type : nullptr;
+    int *tcnt = typed ? nl->tcnt : nullptr;
     if (reset_flags) launch_fill_zero_int(nl->flags, kNumFlags, st);
     if (!nl->periodic) {
-        hipLaunchKernelGGL(k_candidates_open, dim3(xcd_grid(n)), dim3(64), lds, st, n, x, types, rcs2, nl->cap,
-                           nl->cnt, nl->nei, nl->shift, nl->dist, nl->flags, 0);
+        hipLaunchKernelGGL(k_candidates_open, dim3(xcd_grid(n)), dim3(64), lds, st, n, x, check, ktypes, rcs2,
+                           nl->cap, nl->cnt, nl->nei, nl->shift, nl->dist, tcnt, nl->flags, 0);
         launch_reverse(nl, 0, n, st);
         return DP_OK;
     }
     long ncell = (long)nl->nc[0] * nl->nc[1] * nl->nc[2];
     launch_fill_zero_int(nl->cell_cnt, ncell, st);
-    hipLaunchKernelGGL(k_bin, dim3(div_up(n, 256)), dim3(256), 0, st, n, x, types, nl->L[0], nl->L[1],
+    hipLaunchKernelGGL(k_bin, dim3(div_up(n, 256)), dim3(256), 0, st, n, x, check, nl->L[0], nl->L[1],
                        nl->L[2], nl->nc[0], nl->nc[1], nl->nc[2], nl->cellcap,
                        nl->wpos, nl->wrap, nl->cell_cnt,
                        nl->cell_atoms, nl->flags);
@@ -249,8 +276,8 @@ dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, c
     hipLaunchKernelGGL(k_candidates_cells, dim3(xcd_grid(n)), dim3(64), lds, st, n,
                        nl->wpos, nl->wrap, nl->L[0], nl->L[1],
                        nl->L[2], nl->nc[0], nl->nc[1], nl->nc[2], R[0], R[1], R[2], nl->cellcap,
-                       nl->cell_cnt, nl->cell_atoms, rcs2, nl->cap, nl->cnt, nl->nei, nl->shift,
-                       nl->dist, nl->flags, 0);
+                       nl->cell_cnt, nl->cell_atoms, rcs2, nl->cap, ktypes, nl->cnt, nl->nei, nl->shift,
+                       nl->dist, tcnt, nl->flags, 0);
     launch_reverse(nl, 0, n, st);
     return DP_OK;
 }
@@ -267,8 +294,9 @@ dp_status launch_build_nlist_range(dp_nlist *nl, const double *x, int off, int n
     int *cnt = nl->cnt + off, *nei = nl->nei + off * cap, *shift = nl->shift + off * cap;
     float *dist = nl->dist + off * cap;
     if (!L) {
-        hipLaunchKernelGGL(k_candidates_open, dim3(xcd_grid(n)), dim3(64), lds, st, n, xr, (const int *)nullptr, rcs2,
-                           nl->cap, cnt, nei, shift, dist, nl->flags, off);
+        hipLaunchKernelGGL(k_candidates_open, dim3(xcd_grid(n)), dim3(64), lds, st, n, xr, (const int *)nullptr,
+                           (const int *)nullptr, rcs2, nl->cap, cnt, nei, shift, dist, (int *)nullptr, nl->flags,
+                           off);
         return DP_OK;
     }
     int nc[3], R[3];
@@ -286,7 +314,7 @@ dp_status launch_build_nlist_range(dp_nlist *nl, const double *x, int off, int n
                        nl->cell_atoms, nl->flags);
     hipLaunchKernelGGL(k_candidates_cells, dim3(xcd_grid(n)), dim3(64), lds, st, n, nl->wpos + 3L * off, nl->wrap + off, L[0],
                        L[1], L[2], nc[0], nc[1], nc[2], R[0], R[1], R[2], nl->cellcap, nl->cell_cnt, nl->cell_atoms,
-                       rcs2, nl->cap, cnt, nei, shift, dist, nl->flags, off);
+                       rcs2, nl->cap, (const int *)nullptr, cnt, nei, shift, dist, (int *)nullptr, nl->flags, off);
     return DP_OK;
 }
 
@@ -360,20 +388,31 @@ __device__ inline int neg_shift(int v)
 // rev[i][c] = the slot of (i, -shift) in the list of j = nei[i][c], found
 // by distance in j's sorted list (a few float ulps of slack: j computed the
 // same distance from the other side), then a scan of the equal-distance
-// window.  The search starts at c (neighborhoods are alike, so the rank of
-// r_ij in both lists is similar) and gallops outward.  Each pair is searched
-// once, from its lower-indexed side (self-images: from the side with the
-// larger shift code), and both slots are written.  -1 when j's list lacks i,
-// which happens only at the edge of the skin, far outside rcut.  One
-// 64-thread block per atom.
+// window.  With several types the search stays inside the run of i's type in
+// j's list (sorted by distance within the run).  The search starts at c's
+// rank within its own run (neighborhoods are alike, so the rank of r_ij in
+// both lists is similar) and gallops outward.  Each pair is searched once,
+// from its lower-indexed side (self-images: from the side with the larger
+// shift code), and both slots are written.  -1 when j's list lacks i, which
+// happens only at the edge of the skin, far outside rcut.  One 64-thread
+// block per atom.
+__device__ inline int run_start(const int *tcnt, int a, int ty)
+{
+    int s = 0;
+    for (int q = 0; q < ty; q++) s += tcnt[(long)a * kMaxTypes + q];
+    return s;
+}
+
 __global__ void __launch_bounds__(64) k_reverse(int off, int n, int cap, const int *__restrict__ cnt,
                                                 const int *__restrict__ nei, const int *__restrict__ shift,
-                                                const float *__restrict__ dist, short *__restrict__ rev)
+                                                const float *__restrict__ dist, const int *__restrict__ type,
+                                                const int *__restrict__ tcnt, short *__restrict__ rev)
 {
     int ib = xcd_item(blockIdx.x, gridDim.x);
     if (ib >= n) return;
     int i = off + ib;
     int nc = cnt[i];
+    int ti = type ? type[i] : 0;
     for (int c = threadIdx.x; c < nc; c += 64) {
         long ic = (long)i * cap + c;
         int j = nei[ic];
@@ -383,11 +422,17 @@ __global__ void __launch_bounds__(64) k_reverse(int off, int n, int cap, const i
         float r = dist[ic];
         unsigned rb = __float_as_uint(r);
         float lo = __uint_as_float(rb > 8u ? rb - 8u : 0u), hi = __uint_as_float(rb + 8u);
-        const float *dj = dist + (long)j * cap;
-        int ncj = cnt[j];
-        // first index a with dj[a] >= lo: gallop from min(c, ncj - 1), then bisect
+        // j's run of type ti, and c's rank within i's run of j's type
+        int j0 = 0, ncj = cnt[j], crel = c;
+        if (type) {
+            j0 = run_start(tcnt, j, ti);
+            ncj = tcnt[(long)j * kMaxTypes + ti];
+            crel = c - run_start(tcnt, i, type[j]);
+        }
+        const float *dj = dist + (long)j * cap + j0;
+        // first index a with dj[a] >= lo: gallop from min(crel, ncj - 1), then bisect
         int a, b;
-        int p = c < ncj ? c : ncj - 1;
+        int p = crel < ncj ? crel : ncj - 1;
         if (ncj == 0) {
             a = b = 0;
         } else if (dj[p] < lo) {
@@ -418,9 +463,9 @@ __global__ void __launch_bounds__(64) k_reverse(int off, int n, int cap, const i
         }
         int found = -1;
         for (int t = a; t < ncj && dj[t] <= hi; t++) {
-            long jt = (long)j * cap + t;
+            long jt = (long)j * cap + j0 + t;
             if (nei[jt] == i && shift[jt] == want) {
-                found = t;
+                found = j0 + t;
                 break;
             }
         }
@@ -493,8 +538,9 @@ void launch_reverse(dp_nlist *nl, int off, int n, hipStream_t st)
     long m = (long)n * nl->cap;
     hipLaunchKernelGGL(k_fill_short, dim3(div_up(m, 256)), dim3(256), 0, st, nl->rev + (long)off * nl->cap, m,
                        (short)-1);
+    const bool typed = nl->ntypes > 1;
     hipLaunchKernelGGL(k_reverse, dim3(xcd_grid(n)), dim3(64), 0, st, off, n, nl->cap, nl->cnt, nl->nei, nl->shift,
-                       nl->dist, nl->rev);
+                       nl->dist, typed ? nl->type : nullptr, typed ? nl->tcnt : nullptr, nl->rev);
 }
 
 void launch_force_gather(const dp_nlist *nl, int n, int precision, double *force, hipStream_t st)
@@ -506,6 +552,100 @@ void launch_force_gather(const dp_nlist *nl, int n, int precision, double *force
     else
         hipLaunchKernelGGL(k_force_gather<float>, dim3(xcd_grid(div_up(n, 4))), dim3(256), 0, st, n, nl->cap, nl->cnt,
                            nl->nei, nl->rev, (const float *)nl->pg, force);
+}
+
+// ------------------------------------------------- rows grouped by type
+namespace {
+
+// Per block of 256 atoms: copy the types into the list (an out-of-range
+// type is flagged and taken as 0) and count them per type.
+__global__ void __launch_bounds__(256) k_type_count(int n, int ntypes, const int *__restrict__ types,
+                                                    int *__restrict__ type_out, int *__restrict__ blk,
+                                                    int *__restrict__ flags)
+{
+    __shared__ int c[kMaxTypes];
+    if (threadIdx.x < kMaxTypes) c[threadIdx.x] = 0;
+    __syncthreads();
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) {
+        int t = types ? types[i] : 0;
+        if (t < 0 || t >= ntypes) {
+            atomicAdd(&flags[kFlagBadType], 1);
+            t = 0;
+        }
+        type_out[i] = t;
+        atomicAdd(&c[t], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxTypes) blk[(long)blockIdx.x * kMaxTypes + threadIdx.x] = c[threadIdx.x];
+}
+
+// Exclusive prefix of the block counts per type (one thread per type, in
+// block order) and the totals.
+__global__ void k_type_scan(int nblk, int *__restrict__ blk, int *__restrict__ tot)
+{
+    int t = threadIdx.x;
+    if (t >= kMaxTypes) return;
+    int s = 0;
+    for (int b = 0; b < nblk; b++) {
+        int v = blk[(long)b * kMaxTypes + t];
+        blk[(long)b * kMaxTypes + t] = s;
+        s += v;
+    }
+    tot[t] = s;
+}
+
+struct TypeRows {
+    int v[kMaxTypes + 1];
+};
+
+// Row of atom i: its type group's first row, plus the atoms of its type
+// before it (earlier blocks, then earlier threads of its block).
+__global__ void __launch_bounds__(256) k_type_rows(int n, const int *__restrict__ type, const int *__restrict__ blk,
+                                                   TypeRows trow, int *__restrict__ row, int *__restrict__ ratom)
+{
+    __shared__ int ts[256];
+    int i = blockIdx.x * 256 + threadIdx.x;
+    int t = i < n ? type[i] : -1;
+    ts[threadIdx.x] = t;
+    __syncthreads();
+    if (i >= n) return;
+    int r = 0;
+    for (int k = 0; k < (int)threadIdx.x; k++) r += ts[k] == t ? 1 : 0;
+    int rw = trow.v[t] + blk[(long)blockIdx.x * kMaxTypes + t] + r;
+    row[i] = rw;
+    ratom[rw] = i;
+}
+
+__global__ void k_fill_int(int *p, long n, int v)
+{
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+dp_status build_type_layout(dp_nlist *nl, const int *types, hipStream_t st)
+{
+    int n = nl->natoms, T = nl->ntypes;
+    if (T <= 1) return DP_OK;
+    int nblk = div_up(n, 256);
+    int *tot = nl->tblk + (long)nblk * kMaxTypes;
+    hipLaunchKernelGGL(k_type_count, dim3(nblk), dim3(256), 0, st, n, T, types, nl->type, nl->tblk, nl->flags);
+    hipLaunchKernelGGL(k_type_scan, dim3(1), dim3(64), 0, st, nblk, nl->tblk, tot);
+    int cnt[kMaxTypes];
+    DP_HIP(hipGetLastError());
+    DP_HIP(hipStreamSynchronize(st));
+    DP_HIP(hipMemcpy(cnt, tot, sizeof(cnt), hipMemcpyDeviceToHost));
+    TypeRows tr{};
+    for (int t = 0; t < T; t++) tr.v[t + 1] = tr.v[t] + (int)round_up(cnt[t], kRowPad);
+    for (int t = T + 1; t <= kMaxTypes; t++) tr.v[t] = tr.v[T];
+    for (int t = 0; t <= kMaxTypes; t++) nl->trow[t] = tr.v[t];
+    nl->rows = tr.v[T];
+    if ((long)nl->rows > fit_rows(nl->alloc_atoms, T)) return fail(DP_ERR_STATE, "fitting rows exceed the workspace");
+    hipLaunchKernelGGL(k_fill_int, dim3(div_up(nl->rows, 256)), dim3(256), 0, st, nl->ratom, (long)nl->rows, -1);
+    hipLaunchKernelGGL(k_type_rows, dim3(nblk), dim3(256), 0, st, n, nl->type, nl->tblk, tr, nl->row, nl->ratom);
+    return step_check("type_layout", st);
 }
 
 }  // namespace dp

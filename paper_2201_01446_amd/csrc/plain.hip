@@ -48,11 +48,11 @@ __global__ void __launch_bounds__(256) k_plain_env(int natoms, EnvArgs A, real *
     int i = blockIdx.x * (blockDim.x >> 6) + wave;
     NbrLDS<real> L = carve<real>(smem + wave * nbr_lds_bytes<real>(A.sel, ENV_PLAIN), A.sel, ENV_PLAIN);
     bool live = i < natoms;
-    int nn = 0, n_in = 0, oob = 0;
-    if (live) nn = build_env<real, ENV_PLAIN, false>(i, A, L, lane, n_in, oob);
+    int nn = 0, n_in = 0, over = 0, oob = 0;
+    if (live) nn = build_env<real, ENV_PLAIN, false>(i, A, L, lane, n_in, over, oob);
     __syncthreads();
     if (!live) return;
-    record_flags<real>(A, lane, n_in, 0);
+    record_flags<real>(A, lane, n_in, over, 0);
     if (nnei_out && lane == 0) nnei_out[i] = nn;
     for (int k = lane; k < A.sel; k += 64) {
         long row = (long)i * A.sel + k;

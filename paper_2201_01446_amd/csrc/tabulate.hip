@@ -11,7 +11,8 @@
 //
 // Layouts written: tab64[theta][eta][6] (FP64) and tab32[theta][eta][8]
 // (FP32, coefficients 0..5 and two zero pads so a column is two 16-byte
-// loads).
+// loads).  With several atom types the tables of the neighbor types follow
+// each other: type t's interval theta is row t n_int + theta.
 
 #include "dp_internal.h"
 
@@ -20,13 +21,17 @@ namespace dp {
 namespace {
 
 // Net value, slope and curvature at every node: one block of 128 threads
-// per node, thread o owns output column o of each layer.
+// per (node, type), thread o owns output column o of each layer.  emb holds
+// the nets of the types back to back, emb_stride doubles apart.
 __global__ void __launch_bounds__(128) k_nodes(int n_fine, int n_tail, double h, double s_max,
-                                               double h_tail, const double *__restrict__ emb,
-                                               int d1, int d2, int d3, double *__restrict__ out)
+                                               double h_tail, const double *__restrict__ emb_all,
+                                               long emb_stride, int d1, int d2, int d3,
+                                               double *__restrict__ out_all)
 {
     __shared__ double v[3][256], vn[3][256];
     int node = blockIdx.x, o = threadIdx.x;
+    const double *emb = emb_all + blockIdx.y * emb_stride;
+    double *out = out_all + (long)blockIdx.y * (n_fine + n_tail + 1) * d3 * 3;
     double x = node <= n_fine ? node * h : s_max + (node - n_fine) * h_tail;
     const double *W0 = emb, *b0 = W0 + d1, *W1 = b0 + d1, *b1 = W1 + d1 * d2, *W2 = b1 + d2,
                  *b2 = W2 + d2 * d3;
@@ -69,16 +74,18 @@ __global__ void __launch_bounds__(128) k_nodes(int n_fine, int n_tail, double h,
         for (int c = 0; c < 3; c++) out[((long)node * d3 + o) * 3 + c] = v[c][o];
 }
 
-// One thread per (interval, column).
-__global__ void k_hermite(int n_int, int n_fine, double h, double h_tail, int M,
+// One thread per (type, interval, column).
+__global__ void k_hermite(int ntypes, int n_int, int n_fine, double h, double h_tail, int M,
                           const double *__restrict__ nodes, double *__restrict__ tab64,
                           float *__restrict__ tab32)
 {
     long id = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (id >= (long)n_int * M) return;
-    int th = (int)(id / M), e = (int)(id % M);
+    if (id >= (long)ntypes * n_int * M) return;
+    int ty = (int)(id / ((long)n_int * M));
+    int th = (int)(id / M % n_int), e = (int)(id % M);
     double w = th < n_fine ? h : h_tail;
-    const double *L = nodes + ((long)th * M + e) * 3, *R = nodes + ((long)(th + 1) * M + e) * 3;
+    const double *nt = nodes + (long)ty * (n_int + 1) * M * 3;
+    const double *L = nt + ((long)th * M + e) * 3, *R = nt + ((long)(th + 1) * M + e) * 3;
     // end values in the unit variable tau = t / w
     double y0 = L[0], p0 = w * L[1], q0 = w * w * L[2];
     double y1 = R[0], p1 = w * R[1], q1 = w * w * R[2];
@@ -112,10 +119,11 @@ dp_status launch_tabulate(dp_model *m, hipStream_t st)
 {
     const TableInfo &t = m->tab;
     int n_int = t.n_int();
-    hipLaunchKernelGGL(k_nodes, dim3(n_int + 1), dim3(128), 0, st, t.n_fine, t.n_tail, t.h, t.s_max,
-                       t.h_tail, m->emb_d, m->d1, m->d2, m->d3, m->nodes);
-    long nthr = (long)n_int * kM;
-    hipLaunchKernelGGL(k_hermite, dim3(div_up(nthr, 256)), dim3(256), 0, st, n_int, t.n_fine, t.h,
+    long emb_stride = (long)m->d1 * 2 + (long)m->d1 * m->d2 + m->d2 + (long)m->d2 * m->d3 + m->d3;
+    hipLaunchKernelGGL(k_nodes, dim3(n_int + 1, m->ntypes), dim3(128), 0, st, t.n_fine, t.n_tail, t.h, t.s_max,
+                       t.h_tail, m->emb_d, emb_stride, m->d1, m->d2, m->d3, m->nodes);
+    long nthr = (long)m->ntypes * n_int * kM;
+    hipLaunchKernelGGL(k_hermite, dim3(div_up(nthr, 256)), dim3(256), 0, st, m->ntypes, n_int, t.n_fine, t.h,
                        t.h_tail, kM, m->nodes, m->tab64, m->tab32);
     return DP_OK;
 }

@@ -15,8 +15,9 @@ import oracle
 
 
 class LocalSampler:
-    def __init__(self, cfg, params, table, x, box):
+    def __init__(self, cfg, params, table, x, box, types=None):
         self.cfg, self.params, self.table = cfg, params, table
+        self.types = None if types is None else np.ascontiguousarray(types, dtype=np.int32)
         self.x = np.ascontiguousarray(x, dtype=np.float64)
         self.L = np.diag(np.asarray(box, dtype=np.float64).reshape(3, 3)).copy()
         rc = cfg["rcut"]
@@ -53,10 +54,14 @@ class LocalSampler:
         idx, c, _ = self._cut(k, self.cfg["rcut"] + 0.5)
         pos = int(np.nonzero(idx == k)[0][0])
         return oracle.evaluate(self.cfg, self.params, c, None, table=self.table, centers=np.array([pos], np.int32),
-                               forces=False)["e_atom"][0]
+                               forces=False, types=self._types(idx))["e_atom"][0]
+
+    def _types(self, idx):
+        return None if self.types is None else self.types[idx]
 
     def force(self, k):
         idx, c, r = self._cut(k, self.radius)
         pos = int(np.nonzero(idx == k)[0][0])
         cen = np.nonzero(r < self.cfg["rcut"])[0].astype(np.int32)
-        return oracle.evaluate(self.cfg, self.params, c, None, table=self.table, centers=cen)["F"][pos]
+        return oracle.evaluate(self.cfg, self.params, c, None, table=self.table, centers=cen,
+                               types=self._types(idx))["F"][pos]
