@@ -285,6 +285,11 @@ def water(P, nrep, steps, warmup):
                      "energy_drift_eV_per_atom": float((etot[-1] - etot[0]) / N),
                      "kernels": {k: round(vv[0] / max(vv[1], 1), 4) for k, vv in res["kernels"].items()}}
         if name == "fp32":
+            # look-ups past the table end over the run: the random-weight
+            # model has no repulsive core, so atoms in near free flight can
+            # pass closer than the table reaches (s > 1.5, r < 0.67 A), where
+            # G is clamped and the energy is no longer conserved
+            out[name]["table_oob_lookups"] = res["nl"].stats()["table_oob"]
             d = P.descriptor(model, res["nl"], res["x"], precision=P.FP32)
             out["mean_neighbors"] = float(d["nnei"].double().mean().item())
             out["mean_interval_segments"] = float(d["nseg"].double().mean().item())
