@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--no-tanh", action="store_true", help="skip the tabulated-tanh comparison")
     ap.add_argument("--no-water", action="store_true", help="skip the two-type water system")
     ap.add_argument("--water-rep", type=int, default=8, help="replicas per edge of the 192-atom water cell")
+    ap.add_argument("--water-only", action="store_true",
+                    help="run only the water section (--steps timed steps) and print it (for profiling)")
     ap.add_argument("--ablation-steps", type=int, default=10)
     ap.add_argument("--stride-steps", type=int, default=20)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -125,6 +127,9 @@ def main():
     import paper_2201_01446_amd as P
     import synth
 
+    if args.water_only:
+        print(json.dumps({"water": water(P, args.water_rep, args.steps, args.warmup)}))
+        return
     if args.copy_probe_mib:
         a = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
