@@ -102,6 +102,62 @@ namespace {
 
 constexpr int ROWB = 144;   // LDS row pitch (bytes): 128 bytes of K + 16 of padding
 
+typedef __bf16 bf4v __attribute__((ext_vector_type(4)));
+
+// Four consecutive GEMM-operand elements (row gm, columns gn..gn+3) as FP32
+// or as the BF16 [hi | hi | lo] split.
+__device__ inline void store_op4(float *p, long gm, int gn, int N, f4v y)
+{
+    *reinterpret_cast<f4v *>(p + gm * N + gn) = y;
+}
+__device__ inline void store_op4(__bf16 *p, long gm, int gn, int N, f4v y)
+{
+    bf4v hi, lo;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        hi[j] = (__bf16)y[j];
+        lo[j] = (__bf16)(y[j] - (float)hi[j]);
+    }
+    __bf16 *r = p + gm * 3 * N;
+    *reinterpret_cast<bf4v *>(r + gn) = hi;
+    *reinterpret_cast<bf4v *>(r + N + gn) = hi;
+    *reinterpret_cast<bf4v *>(r + 2 * N + gn) = lo;
+}
+
+// The epilogue of an FP32-accumulating GEMM on C[gm][gn..gn+3] (see Epi).
+template <typename TA, int EPI>
+__device__ inline void epi4(const Epi &e, const float *bias, const float *resv, f4v v, int gm, int gn, int N)
+{
+    long idx = (long)gm * N + gn;
+    auto ld = [&](const void *p) { return *reinterpret_cast<const f4v *>((const float *)p + idx); };
+    auto st = [&](void *p, f4v x) { *reinterpret_cast<f4v *>((float *)p + idx) = x; };
+    if constexpr (EPI == EPI_LIN) {
+        st(e.out_r, v);
+    } else if constexpr (EPI == EPI_BWD) {
+        f4v dy = (resv ? *reinterpret_cast<const f4v *>(resv + gn) : ld(e.res)) + v;
+        if (e.out_r) st(e.out_r, dy);
+        f4v t = ld(e.tt), o;
+#pragma unroll
+        for (int j = 0; j < 4; j++) o[j] = dy[j] * (1.f - t[j] * t[j]);
+        store_op4((TA *)e.out_o, gm, gn, N, o);
+    } else {
+        f4v b = *reinterpret_cast<const f4v *>(bias + gn), t;
+#pragma unroll
+        for (int j = 0; j < 4; j++) t[j] = tanh_e(v[j] + b[j], e.tanh_tab);
+        if constexpr (EPI == EPI_T1) {
+            st(e.out_r, t);
+            if (e.out_o) store_op4((TA *)e.out_o, gm, gn, N, t);
+        } else if constexpr (EPI == EPI_T2) {
+            f4v y = ld(e.res) + t;
+            st(e.out_t, t);
+            st(e.out_r, y);
+            if (e.out_o) store_op4((TA *)e.out_o, gm, gn, N, y);
+        } else {
+            st(e.out_t, t);
+        }
+    }
+}
+
 // N 16-byte chunks of a stage held by one thread: chunk r of thread tid is
 // row (tid + 256 r) / 8, byte column 16 ((tid + 256 r) mod 8) of the tile.
 template <int N>
@@ -142,8 +198,11 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const TA *
     constexpr int BM = 32 * TM, BN = 32 * TN;
     constexpr int BK = 128 / sizeof(TA);   // elements of K per row and stage
     constexpr int LA = BM * 8 / 256, LB = BN * 8 / 256;   // 16-byte chunks per thread
-    __shared__ __align__(16) char As[2][BM * ROWB];
-    __shared__ __align__(16) char Bs[2][BN * ROWB];
+    // one LDS block: the double-buffered A and B stages, reused by the
+    // epilogue to stage the C tile
+    __shared__ __align__(16) char smem[2 * BM * ROWB + 2 * BN * ROWB];
+    char (*As)[BM * ROWB] = reinterpret_cast<char (*)[BM * ROWB]>(smem);
+    char (*Bs)[BN * ROWB] = reinterpret_cast<char (*)[BN * ROWB]>(smem + 2 * BM * ROWB);
     int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     // XCD-aware tile order
     int ntn = N / BN, ntm = (M + BM - 1) / BM;
@@ -204,6 +263,40 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const TA *
             rb.store(Bs[buf ^ 1], tid);
         }
         __syncthreads();
+    }
+
+    // FP32-accumulating tiles of the fitting net: C goes through LDS so that
+    // the epilogue reads its operands and writes its results as whole rows
+    // of 16-byte accesses
+    constexpr bool kStaged = !std::is_same<TA, double>::value && TM == 4 && TN == 4 &&
+                             (EPI == EPI_LIN || EPI == EPI_T1 || EPI == EPI_T2 || EPI == EPI_T3 || EPI == EPI_BWD);
+    if constexpr (kStaged) {
+        constexpr int CP = BN + 4;   // staged row pitch (floats)
+        static_assert(BM * CP * 4 <= 2 * BM * ROWB + 2 * BN * ROWB, "C tile must fit the stage buffers");
+        float *Cs = reinterpret_cast<float *>(smem);
+        // (the main loop ends with a barrier: every wave is done with As / Bs)
+#pragma unroll
+        for (int a = 0; a < TM; a++)
+#pragma unroll
+            for (int b = 0; b < TN; b++)
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+                    Cs[(wr * 16 * TM + a * 16 + 4 * q + i) * CP + wc * 16 * TN + b * 16 + m] = acc[a][b][i];
+        __syncthreads();
+        const float *bias4 = e.bias ? (const float *)e.bias + ty * e.vstride : nullptr;
+        const float *resv4 = e.resv ? (const float *)e.resv + ty * e.vstride : nullptr;
+        constexpr int CH = BN / 4;               // 16-byte chunks per row
+        constexpr int NCH = BM * CH / 256;       // chunks per thread
+#pragma unroll 4
+        for (int r = 0; r < NCH; r++) {
+            int k = tid + 256 * r;
+            int row = k / CH, c4 = (k % CH) * 4;
+            int gm = row0 + row, gn = col0 + c4;
+            if (gm >= M) continue;
+            f4v v = *reinterpret_cast<const f4v *>(&Cs[row * CP + c4]);
+            epi4<TA, EPI>(e, bias4, resv4, v, gm, gn, N);
+        }
+        return;
     }
 
     // epilogue: acc[a][b][i] is C[row][col] with col = wc*16TN + b*16 + m and
