@@ -470,7 +470,7 @@ dp_status dp_tabulate(dp_model *m, double s_max, double stride, double tail_max,
     int n = n_fine + n_tail;
     size_t T = (size_t)m->ntypes;
     DP_HIP(hipMalloc(&m->tab64, sizeof(double) * T * n * kM * 6));
-    DP_HIP(hipMalloc(&m->tab32, sizeof(float) * T * n * kM * 8));
+    DP_HIP(hipMalloc(&m->tab32, sizeof(float) * T * n * kM * 6));
     DP_HIP(hipMalloc(&m->nodes, sizeof(double) * T * (n + 1) * kM * 3));
     dp_status s = launch_tabulate(m, (hipStream_t)stream);
     if (s != DP_OK) return s;

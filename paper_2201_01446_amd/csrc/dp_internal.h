@@ -67,7 +67,7 @@ struct dp_model {
     // table
     dp::TableInfo tab;
     double *tab64 = nullptr;     // [ntypes * n_int][M][6]: type t's table at interval t * n_int
-    float *tab32 = nullptr;      // [ntypes * n_int][M][8] (coefficients 0..5, two zero pads)
+    float *tab32 = nullptr;      // [ntypes * n_int][M][6]
     double *nodes = nullptr;     // scratch [ntypes][n_int+1][M][3] of node values g, g', g''
     // tanh of the fitting net in the FP32 and mixed modes: native, or the
     // second-order table [kTanhN][a0, a1, a2, 0] on [0, 8)

@@ -60,13 +60,12 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The 6 coefficients of column c of interval th.
+// The 6 coefficients of column c of interval th (24 bytes, 8-byte aligned).
 __device__ inline void coef_col(const float *tab, int th, int c, float (&a)[6])
 {
-    const float *p = tab + ((long)th * kM + c) * 8;   // FP32 rows: 6 values + 2 pads
-    float4 u = *reinterpret_cast<const float4 *>(p);
-    float2 v = *reinterpret_cast<const float2 *>(p + 4);
-    a[0] = u.x; a[1] = u.y; a[2] = u.z; a[3] = u.w; a[4] = v.x; a[5] = v.y;
+    const float2 *p = reinterpret_cast<const float2 *>(tab + ((long)th * kM + c) * 6);
+    float2 u = p[0], v = p[1], w = p[2];
+    a[0] = u.x; a[1] = u.y; a[2] = v.x; a[3] = v.y; a[4] = w.x; a[5] = w.y;
 }
 __device__ inline void coef_col(const double *tab, int th, int c, double (&a)[6])
 {

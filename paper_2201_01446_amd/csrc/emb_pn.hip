@@ -42,10 +42,10 @@ __device__ inline void pn_coef(const real *tab, int th, int l, real (&a)[CPL][6]
 #pragma unroll
     for (int c = 0; c < CPL; c++) {
         if (sizeof(real) == 4) {
-            const float *p = reinterpret_cast<const float *>(tab) + ((long)th * kM + l + GL * c) * 8;
-            float4 u = *reinterpret_cast<const float4 *>(p);
-            float2 v = *reinterpret_cast<const float2 *>(p + 4);
-            a[c][0] = u.x; a[c][1] = u.y; a[c][2] = u.z; a[c][3] = u.w; a[c][4] = v.x; a[c][5] = v.y;
+            const float2 *p =
+                reinterpret_cast<const float2 *>(reinterpret_cast<const float *>(tab) + ((long)th * kM + l + GL * c) * 6);
+            float2 u = p[0], v = p[1], w = p[2];
+            a[c][0] = u.x; a[c][1] = u.y; a[c][2] = v.x; a[c][3] = v.y; a[c][4] = w.x; a[c][5] = w.y;
         } else {
             const double2 *p =
                 reinterpret_cast<const double2 *>(reinterpret_cast<const double *>(tab) + ((long)th * kM + l + GL * c) * 6);

@@ -160,13 +160,8 @@ __global__ void k_plain_dG(long rows, int sel, real sigma, const V4<real> *__res
 template <typename real>
 __device__ inline void tab_coef(const real *tab, int th, int c, real (&a)[6])
 {
-    if (sizeof(real) == 4) {
-        const real *p = tab + ((long)th * kM + c) * 8;
-        for (int e = 0; e < 6; e++) a[e] = p[e];
-    } else {
-        const real *p = tab + ((long)th * kM + c) * 6;
-        for (int e = 0; e < 6; e++) a[e] = p[e];
-    }
+    const real *p = tab + ((long)th * kM + c) * 6;
+    for (int e = 0; e < 6; e++) a[e] = p[e];
 }
 
 template <typename real>

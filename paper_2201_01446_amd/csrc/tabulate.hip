@@ -9,9 +9,8 @@
 // slope and curvature at either end) and expanded into monomials of the
 // offset t from the left node, a_k = c_k / w^k.
 //
-// Layouts written: tab64[theta][eta][6] (FP64) and tab32[theta][eta][8]
-// (FP32, coefficients 0..5 and two zero pads so a column is two 16-byte
-// loads).  With several atom types the tables of the neighbor types follow
+// Layouts written: tab64[theta][eta][6] (FP64) and tab32[theta][eta][6]
+// (FP32; a column is 24 bytes, three 8-byte loads).  With several atom types the tables of the neighbor types follow
 // each other: type t's interval theta is row t n_int + theta.
 
 #include "dp_internal.h"
@@ -103,14 +102,12 @@ __global__ void k_hermite(int ntypes, int n_int, int n_fine, double h, double h_
     c[5] = -6.0 * y0 - 3.0 * p0 - 0.5 * q0 + 6.0 * y1 - 3.0 * p1 + 0.5 * q1;
     double inv = 1.0 / w, sc = 1.0;
     double *o64 = tab64 + id * 6;
-    float *o32 = tab32 + id * 8;
+    float *o32 = tab32 + id * 6;
     for (int k = 0; k < 6; k++) {
         o64[k] = c[k] * sc;
         o32[k] = (float)(c[k] * sc);
         sc *= inv;
     }
-    o32[6] = 0.0f;
-    o32[7] = 0.0f;
 }
 
 }  // namespace
