@@ -140,18 +140,23 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
         if (a.D_out) launch_op_to_double<TA>(n, kDdim, (const TA *)w.D, typed ? nl->row : nullptr, a.D_out, st);
         // the fitting net's tanh: native, or tabulated in the FP32 and mixed modes when enabled
         const float *ttab = (a.precision != DP_FP64 && m->tanh_on) ? m->tanh_tab : nullptr;
-        e = Epi{c1, nullptr, nullptr, nullptr, w.y1r, w.y1o, nullptr};
+        // when the operand type is the result type (FP32, FP64) the next
+        // layer reads the result array itself; BF16 needs the split copy
+        constexpr bool same = std::is_same<TA, TR>::value;
+        void *y1op = same ? nullptr : w.y1o, *y2op = same ? nullptr : w.y2o;
+        const TA *y1in = (const TA *)(same ? w.y1r : w.y1o), *y2in = (const TA *)(same ? w.y2r : w.y2o);
+        e = Epi{c1, nullptr, nullptr, nullptr, w.y1r, y1op, nullptr};
         e.tanh_tab = ttab;
         e = grouped(e, kFitPad, ks * kDdim);
         DP_TIMED("fit_fwd1", st, launch_gemm<TA, TR>(EPI_T1, mr, kFitPad, ks * kDdim, (const TA *)w.D, (const TA *)fw.V1t, e, st));
-        e = Epi{c2, w.y1r, nullptr, nullptr, w.y2r, w.y2o, w.t2r};
+        e = Epi{c2, w.y1r, nullptr, nullptr, w.y2r, y2op, w.t2r};
         e.tanh_tab = ttab;
         e = grouped(e, kFitPad, ks * kFitPad);
-        DP_TIMED("fit_fwd2", st, launch_gemm<TA, TR>(EPI_T2, mr, kFitPad, ks * kFitPad, (const TA *)w.y1o, (const TA *)fw.V2t, e, st));
+        DP_TIMED("fit_fwd2", st, launch_gemm<TA, TR>(EPI_T2, mr, kFitPad, ks * kFitPad, y1in, (const TA *)fw.V2t, e, st));
         e = Epi{c3, nullptr, nullptr, nullptr, nullptr, nullptr, w.t3r};
         e.tanh_tab = ttab;
         e = grouped(e, kFitPad, ks * kFitPad);
-        DP_TIMED("fit_fwd3", st, launch_gemm<TA, TR>(EPI_T3, mr, kFitPad, ks * kFitPad, (const TA *)w.y2o, (const TA *)fw.V3t, e, st));
+        DP_TIMED("fit_fwd3", st, launch_gemm<TA, TR>(EPI_T3, mr, kFitPad, ks * kFitPad, y2in, (const TA *)fw.V3t, e, st));
     }
     // E_i always; dz3 = w4 (1 - t3^2) when the backward follows
     launch_energy<TA, TR>(typed ? mr : n, (const TR *)w.y2r, (const TR *)w.t3r, w4, rt, w.e_atom,
