@@ -183,7 +183,7 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
                 bool pad = a.mode == DP_FUSED_PADDED;
                 DP_TIMED("emb_bwd_pn", st, launch_emb_bwd_pn(m, a.nl, n, a.x, a.precision, w.T, w.dDr, w.rec, w.rcnt, pad, a.force, w.w_atom, st));
             }
-            DP_TIMED("force_gather", st, launch_force_gather(a.nl, n, a.precision, a.force, st));
+            DP_TIMED("force_gather", st, launch_force_gather(m, a.nl, n, a.x, a.precision, w.rec, w.rcnt, a.force, st));
             if ((s = step_check("emb_bwd", st)) != DP_OK) return s;
         }
     }

@@ -320,9 +320,11 @@ dp_status build_type_layout(dp_nlist *nl, const int *types, hipStream_t st);
 // Reverse slots of the candidate lists of atoms [off, off + n) (after a build).
 void launch_reverse(dp_nlist *nl, int off, int n, hipStream_t st);
 // F_i = (F_i as written by the backward: sum_j dE_i/dr_ij) - sum over the
-// candidates j of i of dE_j/dr_ji, read from the pair gradients at the
-// reverse slot; deterministic (fixed order), no atomics.
-void launch_force_gather(const dp_nlist *nl, int n, int precision, double *force, hipStream_t st);
+// atoms j that list i of dE_j/dr_ji, read from the pair gradients at the
+// reverse slot (rec / rcnt: the forward's neighbor records); deterministic
+// (fixed order), no atomics.
+void launch_force_gather(const dp_model *m, const dp_nlist *nl, int n, const double *x, int precision,
+                         const void *rec, const int *rcnt, double *force, hipStream_t st);
 size_t ws_bytes_for_atoms(int natoms, int precision, int sel, int ntypes);
 dp_status run_compressed(const ComputeArgs &a, hipStream_t st);
 dp_status run_plain(const ComputeArgs &a, hipStream_t st);

@@ -36,8 +36,9 @@ struct EnvArgs {
     // the backward; or NULL
     void *rec;
     int *rcnt;
-    // per candidate slot dE_i/dr_ij (3 reals; cap slots per atom): the forward
-    // zeroes the slots it does not keep, the backward writes the kept ones
+    // per candidate slot dE_i/dr_ij (3 reals; cap slots per atom): the
+    // backward writes the kept ones; the forward zeroes those within rcut
+    // that a neighbor limit cut off (slots beyond rcut are never read)
     void *pg;
     // several atom types: per-type limits, the candidates of each type per
     // atom (the list is grouped by type), one type's interval count
@@ -50,6 +51,21 @@ struct EnvArgs {
 };
 
 __device__ inline long fit_row(const EnvArgs &A, int i) { return A.row ? A.row[i] : i; }
+
+// Kept-neighbor count of an atom as the forward records it: bit 30 set when a
+// neighbor limit cut off some within rcut.
+constexpr int kTruncBit = 1 << 30;
+
+// Displacement r_ij = x_j - x_i + shift and whether |r_ij| < rcut: the one
+// test of every kernel that decides membership (so all decide alike).
+__device__ inline bool within_cut(const double *x, int j, double xi0, double xi1, double xi2, int s, double L0,
+                                  double L1, double L2, double rc2, double &d0, double &d1, double &d2)
+{
+    d0 = (x[3 * j] - xi0) + (int)(signed char)(s & 0xFF) * L0;
+    d1 = (x[3 * j + 1] - xi1) + (int)(signed char)((s >> 8) & 0xFF) * L1;
+    d2 = (x[3 * j + 2] - xi2) + (int)(signed char)((s >> 16) & 0xFF) * L2;
+    return d0 * d0 + d1 * d1 + d2 * d2 < rc2;
+}
 
 // What a kernel keeps per neighbor in its LDS slice.
 enum EnvMode {
@@ -223,11 +239,7 @@ __device__ int scan_candidates(int i, const EnvArgs &A, NbrLDS<real> L, int lane
         int j = 0;
         if (live) {
             j = nei[k];
-            int s = shf[k];
-            d0 = (A.x[3 * j] - xi0) + s8(s, 0) * L0;
-            d1 = (A.x[3 * j + 1] - xi1) + s8(s, 8) * L1;
-            d2 = (A.x[3 * j + 2] - xi2) + s8(s, 16) * L2;
-            in = d0 * d0 + d1 * d1 + d2 * d2 < A.rc2;
+            in = within_cut(A.x, j, xi0, xi1, xi2, shf[k], L0, L1, L2, A.rc2, d0, d1, d2);
         }
         unsigned long long mask = __ballot(in);
         int q = n_in + __popcll(mask & ((1ull << lane) - 1ull));
@@ -237,26 +249,21 @@ __device__ int scan_candidates(int i, const EnvArgs &A, NbrLDS<real> L, int lane
             if (MODE != ENV_FWD) L.j[pos] = j;
             if (MODE == ENV_FWD && A.rec) put_record<real>(A, i, pos, d0, d1, d2, slot_code(k, ty));
         }
-        if (MODE == ENV_FWD && A.pg && live && !in) zero_pg<real>(A, i, k);
         n_in += __popcll(mask);
     }
     if (n_in > lim) {
         // keep the lim nearest by (r^2, j, image); ranks are a permutation
         for (int k = c0 + lane; k < c0 + ct; k += 64) {
             int j = nei[k], s = shf[k];
-            double d0 = (A.x[3 * j] - xi0) + s8(s, 0) * L0;
-            double d1 = (A.x[3 * j + 1] - xi1) + s8(s, 8) * L1;
-            double d2 = (A.x[3 * j + 2] - xi2) + s8(s, 16) * L2;
+            double d0, d1, d2;
+            if (!within_cut(A.x, j, xi0, xi1, xi2, s, L0, L1, L2, A.rc2, d0, d1, d2)) continue;
             double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-            if (!(r2 < A.rc2)) continue;
             int rank = 0;
             for (int q = c0; q < c0 + ct; q++) {
                 int jq = nei[q], sq = shf[q];
-                double e0 = (A.x[3 * jq] - xi0) + s8(sq, 0) * L0;
-                double e1 = (A.x[3 * jq + 1] - xi1) + s8(sq, 8) * L1;
-                double e2 = (A.x[3 * jq + 2] - xi2) + s8(sq, 16) * L2;
+                double e0, e1, e2;
+                if (!within_cut(A.x, jq, xi0, xi1, xi2, sq, L0, L1, L2, A.rc2, e0, e1, e2)) continue;
                 double rq = e0 * e0 + e1 * e1 + e2 * e2;
-                if (!(rq < A.rc2)) continue;
                 bool less = rq < r2 || (rq == r2 && (jq < j || (jq == j && sq < s)));
                 rank += less ? 1 : 0;
             }
@@ -306,7 +313,7 @@ __device__ int build_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane, int 
             c0 += ct;
         }
     }
-    if (MODE == ENV_FWD && A.rec && lane == 0) A.rcnt[i] = nn;
+    if (MODE == ENV_FWD && A.rec && lane == 0) A.rcnt[i] = nn | (over ? kTruncBit : 0);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -321,7 +328,7 @@ __device__ int build_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane, int 
 template <typename real, int MODE = ENV_BWD>
 __device__ int load_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane)
 {
-    int nn = A.rcnt[i];
+    int nn = A.rcnt[i] & ~kTruncBit;
     const V4<real> *rec = reinterpret_cast<const V4<real> *>(A.rec) + (long)i * A.sel;
     for (int k = lane; k < nn; k += 64) {
         V4<real> r = rec[k];

@@ -474,8 +474,14 @@ __global__ void __launch_bounds__(64) k_reverse(int off, int n, int cap, const i
     }
 }
 
-// One 64-lane wave per atom, lanes over its candidates, four candidates per
-// lane in flight (their indices first, then their pair gradients).
+// Per atom i (one wave): F_i -= sum of dE_j/dr_ji over the atoms j that
+// list i, read from j's pair-gradient slot for i (the reverse slot).  When i
+// kept every neighbor within rcut, those j are exactly i's kept neighbors
+// (membership within rcut is symmetric and their limits kept i, or they
+// zeroed its slot), so only the forward's records are visited; otherwise
+// every candidate within rcut, by the forward's own membership test.  Lanes
+// take neighbors, four in flight (indices first, then pair gradients); the
+// order of the sum is fixed.
 template <typename real>
 __device__ inline void add_pg(const real *p, double &f0, double &f1, double &f2)
 {
@@ -492,29 +498,65 @@ __device__ inline void add_pg(const real *p, double &f0, double &f1, double &f2)
 }
 
 template <typename real>
-__global__ void __launch_bounds__(256) k_force_gather(int n, int cap, const int *__restrict__ cnt,
-                                                      const int *__restrict__ nei, const short *__restrict__ rev,
-                                                      const real *__restrict__ pg, double *__restrict__ force)
+__global__ void __launch_bounds__(256) k_force_gather(int n, EnvArgs A, const short *__restrict__ rev,
+                                                      double *__restrict__ force)
 {
     constexpr int ST = sizeof(real) == 4 ? 4 : 3;   // reals per pair-gradient slot
     int lane = threadIdx.x & 63;
     int i = xcd_item(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     if (i >= n) return;
-    int nc = cnt[i];
-    const int *ni = nei + (long)i * cap;
+    const long cap = A.cap;
+    const int *ni = A.nei + (long)i * cap;
     const short *ri = rev + (long)i * cap;
+    const real *pg = reinterpret_cast<const real *>(A.pg);
     double f0 = 0, f1 = 0, f2 = 0;
-    for (int c0 = 0; c0 < nc; c0 += 256) {
-        long off[4];
+    int code = A.rcnt[i];
+    if (!(code & kTruncBit)) {
+        int nn = code;
+        const V4<real> *rec = reinterpret_cast<const V4<real> *>(A.rec) + (long)i * A.sel;
+        for (int k0 = 0; k0 < nn; k0 += 256) {
+            long off[4];
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            int c = c0 + 64 * u + lane;
-            int r = c < nc ? ri[c] : -1;
-            off[u] = r < 0 ? -1 : ((long)ni[c] * cap + r) * ST;
+            for (int u = 0; u < 4; u++) {
+                int k = k0 + 64 * u + lane;
+                off[u] = -1;
+                if (k < nn) {
+                    int c = record_slot(rec[k].w) & 0xFFFFFF;
+                    int r = ri[c];
+                    off[u] = r < 0 ? -1 : ((long)ni[c] * cap + r) * ST;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (off[u] >= 0) add_pg<real>(pg + off[u], f0, f1, f2);
         }
+    } else {
+        int nc = A.cnt[i];
+        const int *si = A.shift + (long)i * cap;
+        double xi0 = A.x[3 * i], xi1 = A.x[3 * i + 1], xi2 = A.x[3 * i + 2];
+        double L0 = A.L0, L1 = A.L1, L2 = A.L2;
+        if (A.atomL) {
+            L0 = A.atomL[3 * i];
+            L1 = A.atomL[3 * i + 1];
+            L2 = A.atomL[3 * i + 2];
+        }
+        for (int c0 = 0; c0 < nc; c0 += 256) {
+            long off[4];
 #pragma unroll
-        for (int u = 0; u < 4; u++)
-            if (off[u] >= 0) add_pg<real>(pg + off[u], f0, f1, f2);
+            for (int u = 0; u < 4; u++) {
+                int c = c0 + 64 * u + lane;
+                off[u] = -1;
+                if (c < nc) {
+                    int j = ni[c], r = ri[c];
+                    double d0, d1, d2;
+                    if (r >= 0 && within_cut(A.x, j, xi0, xi1, xi2, si[c], L0, L1, L2, A.rc2, d0, d1, d2))
+                        off[u] = ((long)j * cap + r) * ST;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (off[u] >= 0) add_pg<real>(pg + off[u], f0, f1, f2);
+        }
     }
     for (int o = 32; o > 0; o >>= 1) {
         f0 += __shfl_xor(f0, o);
@@ -543,15 +585,20 @@ void launch_reverse(dp_nlist *nl, int off, int n, hipStream_t st)
                        nl->dist, typed ? nl->type : nullptr, typed ? nl->tcnt : nullptr, nl->rev);
 }
 
-void launch_force_gather(const dp_nlist *nl, int n, int precision, double *force, hipStream_t st)
+void launch_force_gather(const dp_model *m, const dp_nlist *nl, int n, const double *x, int precision,
+                         const void *rec, const int *rcnt, double *force, hipStream_t st)
 {
     if (n <= 0) return;
+    EnvArgs A = make_env_args(m, nl, x);
+    A.rec = const_cast<void *>(rec);
+    A.rcnt = const_cast<int *>(rcnt);
+    A.pg = nl->pg;
     if (precision == DP_FP64)
-        hipLaunchKernelGGL(k_force_gather<double>, dim3(xcd_grid(div_up(n, 4))), dim3(256), 0, st, n, nl->cap, nl->cnt,
-                           nl->nei, nl->rev, (const double *)nl->pg, force);
+        hipLaunchKernelGGL(k_force_gather<double>, dim3(xcd_grid(div_up(n, 4))), dim3(256), 0, st, n, A, nl->rev,
+                           force);
     else
-        hipLaunchKernelGGL(k_force_gather<float>, dim3(xcd_grid(div_up(n, 4))), dim3(256), 0, st, n, nl->cap, nl->cnt,
-                           nl->nei, nl->rev, (const float *)nl->pg, force);
+        hipLaunchKernelGGL(k_force_gather<float>, dim3(xcd_grid(div_up(n, 4))), dim3(256), 0, st, n, A, nl->rev,
+                           force);
 }
 
 // ------------------------------------------------- rows grouped by type
