@@ -286,14 +286,23 @@ __global__ void __launch_bounds__(256) k_vv_partial(long n3, const double *__res
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-__global__ void k_thermo_final(int nblk, const double *__restrict__ part, const double *__restrict__ energy,
-                               double *row)
+// Kinetic energy from the 256 partials (a tree in LDS, fixed order) and the
+// potential energy into one thermo row.
+__global__ void __launch_bounds__(256) k_thermo_final(int nblk, const double *__restrict__ part,
+                                                      const double *__restrict__ energy, double *row)
 {
-    if (threadIdx.x != 0) return;
-    double s = 0;
-    for (int b = 0; b < nblk; b++) s += part[b];
-    row[0] = *energy;
-    row[1] = s;
+    __shared__ double sh[256];
+    int t = threadIdx.x;
+    sh[t] = t < nblk ? part[t] : 0.0;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    if (t == 0) {
+        row[0] = *energy;
+        row[1] = sh[0];
+    }
 }
 
 }  // namespace
@@ -315,7 +324,7 @@ void launch_thermo(const double *v, const double *energy, int n, const int *type
                    double *part, hipStream_t st)
 {
     hipLaunchKernelGGL(k_vv_partial, dim3(256), dim3(256), 0, st, 3L * n, v, type, ke, part);
-    hipLaunchKernelGGL(k_thermo_final, dim3(1), dim3(64), 0, st, 256, part, energy, row);
+    hipLaunchKernelGGL(k_thermo_final, dim3(1), dim3(256), 0, st, 256, part, energy, row);
 }
 
 double acc_unit() { return kAcc; }

@@ -452,18 +452,22 @@ __global__ void __launch_bounds__(256) k_reduce_partial(int n, const double *__r
     if (threadIdx.x < 10) part[blockIdx.x * 10 + threadIdx.x] = sh[0][threadIdx.x];
 }
 
-__global__ void __launch_bounds__(64) k_reduce_final(int nblk, const double *__restrict__ part,
-                                                     double *energy, double *virial)
+// Sum of the kRedBlocks partials: one per thread, then a tree in LDS
+// (a fixed order).
+__global__ void __launch_bounds__(256) k_reduce_final(int nblk, const double *__restrict__ part,
+                                                      double *energy, double *virial)
 {
-    int q = threadIdx.x;
-    if (q >= 10) return;
-    double s = 0;
-    for (int b = 0; b < nblk; b++) s += part[b * 10 + q];
-    if (q == 0) {
-        if (energy) *energy = s;
-    } else if (virial) {
-        virial[q - 1] = s;
+    __shared__ double sh[256][11];
+    int t = threadIdx.x;
+    for (int q = 0; q < 10; q++) sh[t][q] = t < nblk ? part[t * 10 + q] : 0.0;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s)
+            for (int q = 0; q < 10; q++) sh[t][q] += sh[t + s][q];
+        __syncthreads();
     }
+    if (t == 0 && energy) *energy = sh[0][0];
+    if (t >= 1 && t < 10 && virial) virial[t - 1] = sh[0][t];
 }
 
 template <typename T>
@@ -561,7 +565,8 @@ void launch_reduce(int n, const double *e_atom, const double *w_atom, double *pa
                    double *virial, hipStream_t st)
 {
     hipLaunchKernelGGL(k_reduce_partial, dim3(kRedBlocks), dim3(256), 0, st, n, e_atom, w_atom, part);
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, st, kRedBlocks, part, energy, virial);
+    static_assert(kRedBlocks <= 256, "one partial per thread");
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, kRedBlocks, part, energy, virial);
 }
 
 template <typename T>
