@@ -380,7 +380,7 @@ def stride_sweep(P, cfg, params, x0, v0, box, steps):
     for h in (0.1, 0.01, 0.001):
         m = P.Model(cfg, params).tabulate(0.7, h, 1.5, 0.1)
         nint = int(round(0.7 / h)) + 8
-        row = {"stride": h, "intervals": nint, "table_bytes_fp32": nint * 128 * 8 * 4,
+        row = {"stride": h, "intervals": nint, "table_bytes_fp32": nint * 128 * 6 * 4,
                "table_bytes_fp64": nint * 128 * 6 * 8}
         for prec, tag in ((P.FP64, "fp64"), (P.FP32, "fp32")):
             o = P.compute(m, nl, x, precision=prec)
