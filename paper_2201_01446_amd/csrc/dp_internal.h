@@ -23,15 +23,17 @@ constexpr int kMaxTypes = DP_MAX_TYPES;
 // Per-type block of the fitting net's vectors: c1, c2, c3, w4 (kFitPad each), b4
 constexpr int kFitB = 4 * kFitPad + 64;
 
-// Device-side sticky counters of a neighbor list.
+// Device-side sticky counters of a neighbor list, each on a 128-byte line of
+// its own (atomics on one counter must not delay reads of another).
+constexpr int kFlagStride = 32;
 enum Flag {
-    kFlagMaxNei = 0,       // atomicMax of neighbors within rcut
-    kFlagSelOverflow = 1,  // atoms with more than sel neighbors within rcut
-    kFlagTableOob = 2,     // table look-ups past the last node
-    kFlagCapOverflow = 3,  // atoms whose candidate list hit cap
-    kFlagCellOverflow = 4, // atoms that did not fit their cell
-    kFlagBadType = 5,      // atoms with a type outside [0, ntypes)
-    kNumFlags = 8
+    kFlagMaxNei = 0 * kFlagStride,        // atomicMax of neighbors within rcut
+    kFlagSelOverflow = 1 * kFlagStride,   // atoms with more than sel neighbors within rcut
+    kFlagTableOob = 2 * kFlagStride,      // table look-ups past the last node
+    kFlagCapOverflow = 3 * kFlagStride,   // atoms whose candidate list hit cap
+    kFlagCellOverflow = 4 * kFlagStride,  // atoms that did not fit their cell
+    kFlagBadType = 5 * kFlagStride,       // atoms with a type outside [0, ntypes)
+    kNumFlags = 8 * kFlagStride
 };
 
 struct TableInfo {

@@ -355,7 +355,11 @@ __device__ inline void record_flags(const EnvArgs &A, int lane, int n_in, int ov
     // wave-wide sum of oob
     for (int off = 32; off > 0; off >>= 1) oob += __shfl_xor(oob, off);
     if (lane == 0) {
-        atomicMax(&A.flags[kFlagMaxNei], n_in);
+        // the maximum only grows: an atomic only when this atom would raise
+        // the value read (one address shared by every wave of the launch, so
+        // an atomic per wave would serialise them)
+        int seen = __hip_atomic_load(&A.flags[kFlagMaxNei], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (n_in > seen) atomicMax(&A.flags[kFlagMaxNei], n_in);
         if (over) atomicAdd(&A.flags[kFlagSelOverflow], 1);
         if (oob) atomicAdd(&A.flags[kFlagTableOob], oob);
     }
