@@ -166,20 +166,28 @@ def test_open_clusters(P, model, cu_cfg, cu_params, otab):
         assert np.max(np.abs(got["F"] - ref["F"])) <= 1e-12 + 1e-10 * np.max(np.abs(ref["F"]))
 
 
-def test_sel_overflow_keeps_nearest(P, cu_params):
-    """More neighbors than sel: the sel nearest are kept, as in the oracle."""
-    cfg = synth.copper_model_config(sel=150)
+@pytest.mark.parametrize("sel", [150, 179])
+def test_sel_overflow_keeps_nearest(P, cu_params, sel):
+    """More neighbors than sel: the sel nearest are kept, as in the oracle.
+    sel = 150 cuts every atom's list; sel = 179 cuts about half of them, so
+    the force gather takes both of its paths (kept pairs only, and every
+    candidate within rcut) in one launch."""
+    cfg = synth.copper_model_config(sel=sel)
     p = synth.model_params(cfg)
     m = P.Model(cfg, p).tabulate(S_MAX, H, TAIL, H_TAIL)
     tab = oracle.Table(cfg, p, S_MAX, H, TAIL, H_TAIL)
     x, box = synth.copper(3, 0.1, 17)
     ref = oracle.evaluate(cfg, p, x, box, table=tab)
     assert ref["dropped"] > 0
-    got, nl = run(P, m, x, box, 0)
-    check_against(ref, got, 0, len(x))
-    st = nl.stats()
-    assert st["sel_overflow"] == int(np.sum(ref["nnei"] > 150))
-    assert st["max_nei"] == int(np.max(ref["nnei"]))
+    n_over = int(np.sum(ref["nnei"] > sel))
+    if sel == 179:
+        assert 0 < n_over < len(x)
+    for precision in (0, 1):
+        got, nl = run(P, m, x, box, precision)
+        check_against(ref, got, precision, len(x))
+        st = nl.stats()
+        assert st["sel_overflow"] == n_over
+        assert st["max_nei"] == int(np.max(ref["nnei"]))
 
 
 def test_forces_are_minus_gradient_of_gpu_energy(P, model):
