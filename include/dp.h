@@ -189,20 +189,22 @@ dp_status dp_energy_backward(dp_model *model, dp_nlist *nlist, int natoms, const
                              void *stream);
 
 /* Intermediate results for testing: per atom the number of neighbors used
- * (nnei_d, int32), the number of runs of equal table interval in its
- * distance-sorted neighbor list (nseg_d, int32; compressed mode only, the
+ * (nnei_d, int32: those within rcut, after the neighbor limits), the number
+ * of runs of equal table interval in its neighbor list, grouped by type and
+ * distance-sorted within a type (nseg_d, int32; compressed mode only, the
  * work unit of the kernels' interval-moment contraction; left untouched in
- * plain mode), T = desc_scale * R^T G (T_d, natoms x 4 x M, row k of the 4
- * environment columns) and D = (T<)^T T (D_d, natoms x M< x M), all FP64
- * copies; any may be NULL. */
+ * the other modes), T = desc_scale * R^T G (T_d, natoms x 4 x M, row k of the
+ * 4 environment columns) and D = (T<)^T T (D_d, natoms x M< x M, in atom
+ * order), all FP64 copies; any may be NULL. */
 dp_status dp_descriptor(dp_model *model, dp_nlist *nlist, int natoms, const double *coords_d,
                         const double *box_h, int mode, int precision, int *nnei_d, int *nseg_d,
                         double *T_d, double *D_d, void *stream);
 
 /* Sticky counters of the list since its last build (synchronises):
  * max_nei: most neighbors within rcut seen for one atom; n_sel_overflow:
- * atoms that had more than sel; n_table_oob: look-ups past the table end;
- * n_cap_overflow: atoms whose candidate list was truncated at build. */
+ * atoms that had more than sel (several types: more than sel_t of some
+ * type), counted once per evaluation; n_table_oob: look-ups past the table
+ * end; n_cap_overflow: atoms whose candidate list was truncated at build. */
 dp_status dp_nlist_stats(dp_nlist *nlist, int *max_nei, int *n_sel_overflow, int *n_table_oob,
                          int *n_cap_overflow);
 
