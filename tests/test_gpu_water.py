@@ -201,3 +201,25 @@ def test_water_errors(P, model, w_cfg, w_params):
         P.Model(dict(w_cfg, sel=100), w_params)          # sel != sum of sel_t
     with pytest.raises(ValueError):
         P.nve_run(model, nl, xd, dev(np.zeros_like(x)), box, synth.M_O, 0.5, 1, types=dev(t, torch.int32))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_water_autograd_matches_compute(P, model, otab, w_cfg, w_params, precision):
+    """The autograd function on the two-type system: E and dE/dx equal the
+    one-call step's E and -F (the same kernels, split at the fitting net),
+    and, in FP64, the oracle's."""
+    from paper_2201_01446_amd.autograd import DPEnergy
+    x, t, box = synth.water(1, sigma=0.05)
+    x, t = shuffled(x, t, 9)
+    xd = dev(x).requires_grad_(True)
+    nl = P.NeighborList(model, xd.detach(), box, skin=2.0, types=dev(t, torch.int32))
+    E = DPEnergy.apply(xd, model, nl, precision, P.COMPRESSED)
+    (g,) = torch.autograd.grad(E.sum(), xd)
+    one = P.compute(model, nl, xd.detach(), precision=precision)
+    torch.cuda.synchronize()
+    assert float(E.item()) == float(one["E"].item())
+    np.testing.assert_array_equal(g.cpu().numpy(), -one["F"].cpu().numpy())
+    if precision == 0:
+        ref = oracle.evaluate(w_cfg, w_params, x, box, table=otab, types=t)
+        assert abs(float(E.item()) - ref["E"]) <= 1e-10 * abs(ref["E"])
+        np.testing.assert_allclose(-g.cpu().numpy(), ref["F"], rtol=0, atol=1e-10 * np.max(np.abs(ref["F"])))
