@@ -61,3 +61,14 @@ def test_bad_arguments_are_rejected():
     assert _lib.lib.dp_compute(None, None, 0, None, None, None, 0, 0, None, None, None, None, None) == -1
     assert _lib.lib.dp_model_destroy(None) == 0
     assert _lib.lib.dp_nlist_destroy(None) == 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU; --gpus 2 exits with a message and status 2."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
