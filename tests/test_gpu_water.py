@@ -127,17 +127,18 @@ def test_water_per_neighbor_modes(P, model, otab, w_cfg, w_params, mode):
     check(ref, got, 0, len(x))
 
 
-def test_water_per_type_truncation(P, w_cfg, w_params):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_water_per_type_truncation(P, w_cfg, w_params, precision):
     """Limits below the counts (20 O, 40 H): of each type the nearest are kept."""
     cfg = dict(w_cfg, sel_t=(20, 40), sel=60)
     m = P.Model(cfg, w_params).tabulate(*TAB)
     tab = oracle.Table(cfg, w_params, *TAB)
     x, t, box = synth.water(1, sigma=0.05)
     x, t = shuffled(x, t, 5)
-    got, nl = run(P, m, x, t, box, 0)
+    got, nl = run(P, m, x, t, box, precision)
     ref = oracle.evaluate(cfg, w_params, x, box, table=tab, types=t)
     assert ref["dropped"] > 0
-    check(ref, got, 0, len(x))
+    check(ref, got, precision, len(x))
     assert nl.stats()["sel_overflow"] == len(x)
 
 
