@@ -42,7 +42,7 @@ typedef enum {
     DP_ERR_HIP = -2,         /* a HIP runtime call failed                       */
     DP_ERR_OOM = -3,         /* device allocation failed                        */
     DP_ERR_CAPACITY = -4,    /* a neighbor-list or cell capacity was exceeded   */
-    DP_ERR_UNSUPPORTED = -5, /* a valid request this build does not implement   */
+    DP_ERR_UNSUPPORTED = -5, /* a valid request the library does not implement  */
     DP_ERR_STATE = -6,       /* call order violated (e.g. no table yet)         */
     DP_ERR_NONFINITE = -7    /* a non-finite energy was produced                */
 } dp_status;
