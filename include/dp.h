@@ -148,6 +148,11 @@ dp_status dp_table_download(dp_model *model, double *coef_h, int *n_int);
  * atom's type in [0, ntypes) (NULL: all 0); with several types every list is
  * grouped by neighbor type, nearest first within a type, and the list keeps
  * its own copy of the types (they are fixed for the life of the list).
+ * The list also keeps the positions it was built at and, per atom and type,
+ * how many candidates lay within rcut + skin/4: an evaluation whose atoms
+ * have all moved at most skin/8 - 5e-4 A since then scans only those (the
+ * others are provably beyond rcut); any other evaluation scans every
+ * candidate.  Results do not depend on which scan runs.
  * Synchronises once to check the capacity flags; DP_ERR_CAPACITY when an
  * atom has more than 1024 candidates, DP_ERR_ARG for a type out of range. */
 dp_status dp_build_nlist(dp_model *model, int natoms, const double *coords_d, const int *types_d,

@@ -145,7 +145,7 @@ void free_nlist_arrays(dp_nlist *nl)
 {
     void *p[] = {nl->cell_cnt, nl->cell_atoms, nl->wpos, nl->wrap, nl->cnt, nl->nei, nl->shift,
                  nl->dist, nl->rev, nl->pg, nl->flags, nl->ws, nl->ws_plain, nl->force_tmp, nl->scal,
-                 nl->type, nl->tcnt, nl->row, nl->ratom, nl->tblk};
+                 nl->type, nl->tcnt, nl->row, nl->ratom, nl->tblk, nl->x0, nl->inner, nl->disp};
     for (void *q : p)
         if (q) (void)hipFree(q);
 }
@@ -218,10 +218,13 @@ dp_status prepare_nlist(const dp_model *m, int natoms, const double *box, double
     if (grow) {
         int alloc = natoms > nl->alloc_atoms ? natoms : nl->alloc_atoms;
         int capn = cap > nl->cap ? cap : nl->cap;
-        void *p[] = {nl->wpos, nl->wrap, nl->cnt, nl->nei, nl->shift, nl->dist, nl->rev, nl->pg, nl->force_tmp};
+        void *p[] = {nl->wpos, nl->wrap, nl->cnt, nl->nei, nl->shift, nl->dist, nl->rev, nl->pg, nl->force_tmp,
+                     nl->x0, nl->inner};
         for (void *q : p)
             if (q) DP_HIP(hipFree(q));
         DP_HIP(hipMalloc(&nl->wpos, sizeof(double) * 3 * (size_t)alloc));
+        DP_HIP(hipMalloc(&nl->x0, sizeof(double) * 3 * (size_t)alloc));
+        DP_HIP(hipMalloc(&nl->inner, sizeof(int) * kMaxTypes * (size_t)alloc));
         DP_HIP(hipMalloc(&nl->wrap, sizeof(int) * (size_t)alloc));
         DP_HIP(hipMalloc(&nl->cnt, sizeof(int) * (size_t)alloc));
         DP_HIP(hipMalloc(&nl->nei, sizeof(int) * (size_t)alloc * capn));
@@ -254,6 +257,8 @@ dp_status prepare_nlist(const dp_model *m, int natoms, const double *box, double
         DP_HIP(hipMemset(nl->flags, 0, sizeof(int) * kNumFlags));
     }
     if (!nl->scal) DP_HIP(hipMalloc(&nl->scal, sizeof(double) * 512));
+    if (!nl->disp) DP_HIP(hipMalloc(&nl->disp, sizeof(unsigned long long)));
+    nl->margin = 0.25 * skin;
     nl->natoms = natoms;
     dp_status s = ensure_ws(nl, DP_FP64, m->cfg.sel);
     if (s != DP_OK) return s;
@@ -668,7 +673,7 @@ dp_status dp_footprint_bytes(const dp_model *m, int natoms, size_t *bytes)
 {
     if (!m || natoms < 0 || !bytes) return fail(DP_ERR_ARG, "bad argument");
     // candidates (index, shift, distance, reverse slot, pair gradient), positions, boxes, counts
-    size_t per = (size_t)kCapMax * (4 + 4 + 4 + 2 + 24) + 3 * 8 + 3 * 8 + 4 * 4 + 3 * 8;
+    size_t per = (size_t)kCapMax * (4 + 4 + 4 + 2 + 24) + 3 * 8 + 3 * 8 + 4 * 4 + 3 * 8 + 3 * 8 + 4 * kMaxTypes;
     size_t ws = std::max(ws_bytes_for_atoms(natoms, DP_FP64, m->cfg.sel, m->cfg.ntypes),
                          ws_bytes_for_atoms(natoms, DP_MIXED_BF16, m->cfg.sel, m->cfg.ntypes));
     if (m->cfg.ntypes > 1) per += 4 * (2 + kMaxTypes) + 4;   // type, row, per-type counts, row map

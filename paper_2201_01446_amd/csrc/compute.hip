@@ -124,6 +124,7 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
     }
     for (int t = 0; t < kMaxTypes; t++) rt.b4[t] = m->b4[t];
     bool fwd = a.phase != 2, bwd = a.need_forces && a.phase != 1;
+    launch_displacement(nl, n, a.x, st);   // decides the early end of the candidate scans
     if (fwd) {
         if (PLAIN) {
             bool tab = a.mode == DP_TAB_UNFUSED;

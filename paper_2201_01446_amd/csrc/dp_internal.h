@@ -102,6 +102,14 @@ struct dp_nlist {
     short *rev = nullptr;    // [natoms * cap], slot of (i, -shift) in j's list, or -1
     void *pg = nullptr;      // [natoms * cap * 3] reals: dE_i/dr_ij per candidate slot
     int *flags = nullptr;    // [kNumFlags]
+    // exact early end of the candidate scan: the positions at build, per atom
+    // and type the candidates whose build distance is <= rcut + margin (a
+    // prefix of the sorted run), and the largest displacement since the build
+    // (FP64 bits, set before each evaluation); none of these in batch lists
+    double *x0 = nullptr;                 // [natoms * 3]
+    int *inner = nullptr;                 // [natoms * kMaxTypes]
+    unsigned long long *disp = nullptr;   // [1]
+    double margin = 0;                    // skin / 4
     // several types: each atom's type, its candidates per type (the list is
     // grouped by type), and the fitting net's row of each atom: rows are
     // grouped by center type, group t at [trow[t], trow[t + 1]), each group
@@ -201,6 +209,8 @@ __device__ inline int xcd_item(int b, int grid) { return (b % kXcd) * (grid / kX
 void launch_fill_zero(double *p, long n, hipStream_t st);
 void launch_fill_zero_bytes(void *p, size_t nbytes, hipStream_t st);
 void launch_fill_zero_int(int *p, long n, hipStream_t st);
+// The largest |x_i - x0_i| into nl->disp (no-op for lists without x0).
+void launch_displacement(const dp_nlist *nl, int n, const double *x, hipStream_t st);
 dp_status launch_tabulate(dp_model *m, hipStream_t st);
 constexpr int kTanhN = 1024;   // tanh table intervals of width 1/128 on [0, 8)
 void launch_tanh_table(float *tab, hipStream_t st);

@@ -48,9 +48,19 @@ struct EnvArgs {
     int n_int;
     // fitting-net row of each atom (NULL: the atom index)
     const int *row;
+    // early end of the scan: per atom and type the prefix of candidates whose
+    // build distance is <= rcut + margin, the largest displacement since the
+    // build (FP64 bits); NULL: every candidate is scanned
+    const int *inner;
+    const unsigned long long *disp;
+    double margin;
 };
 
 __device__ inline long fit_row(const EnvArgs &A, int i) { return A.row ? A.row[i] : i; }
+
+// Angstrom of slack in the early end of the candidate scan (far above the
+// rounding of an FP32 distance of a few tens of Angstrom).
+constexpr double kScanSlack = 1e-3;
 
 // Kept-neighbor count of an atom as the forward records it: bit 30 set when a
 // neighbor limit cut off some within rcut.
@@ -302,8 +312,15 @@ __device__ int build_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane, int 
         L1 = A.atomL[3 * i + 1];
         L2 = A.atomL[3 * i + 2];
     }
+    // A candidate past the prefix was farther than rcut + margin at build;
+    // both atoms moved at most disp since, so it is now farther than
+    // rcut + margin - 2 disp, and beyond rcut while 2 disp + slack <= margin
+    // (the slack covers the FP32 rounding of the stored distance).
+    bool prefix = false;
+    if (A.inner) prefix = 2.0 * __longlong_as_double((long long)*A.disp) + kScanSlack <= A.margin;
     int nn = 0, n_in = 0, over = 0;
     if (A.ntypes <= 1) {
+        if (prefix) nc = A.inner[(long)i * kMaxTypes];
         n_in = scan_candidates<real, MODE>(i, A, L, lane, 0, nc, A.sel, 0, 0, xi0, xi1, xi2, L0, L1, L2);
         nn = n_in < A.sel ? n_in : A.sel;
         over = n_in > A.sel;
@@ -311,8 +328,9 @@ __device__ int build_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane, int 
         int c0 = 0;
         for (int ty = 0; ty < A.ntypes; ty++) {
             int ct = A.tcnt[(long)i * kMaxTypes + ty];
+            int cs = prefix ? A.inner[(long)i * kMaxTypes + ty] : ct;
             int lim = A.sel_t[ty];
-            int m = scan_candidates<real, MODE>(i, A, L, lane, c0, ct, lim, nn, ty, xi0, xi1, xi2, L0, L1, L2);
+            int m = scan_candidates<real, MODE>(i, A, L, lane, c0, cs, lim, nn, ty, xi0, xi1, xi2, L0, L1, L2);
             nn += m < lim ? m : lim;
             n_in += m;
             over |= m > lim;
@@ -425,6 +443,9 @@ inline EnvArgs make_env_args(const dp_model *m, const dp_nlist *nl, const double
     for (int t = 0; t < kMaxTypes; t++) A.sel_t[t] = t < m->cfg.ntypes ? m->cfg.sel_t[t] : 0;
     A.tcnt = nl->ntypes > 1 ? nl->tcnt : nullptr;
     A.n_int = m->tab.n_int();
+    A.inner = nl->x0 ? nl->inner : nullptr;
+    A.disp = nl->disp;
+    A.margin = nl->margin;
     A.row = nl->ntypes > 1 ? nl->row : nullptr;
     return A;
 }

@@ -232,11 +232,74 @@ __global__ void __launch_bounds__(64) k_candidates_open(int n, const double *__r
     finish_atom(i, count, cap, keys, nullptr, 0, out_cnt, out_nei, out_shift, out_dist, out_tcnt, flags, joff);
 }
 
+// Per atom (one wave) and type run: how many candidates have a build
+// distance <= lim.  The runs are sorted by distance, so these are a prefix.
+__global__ void __launch_bounds__(256) k_inner(int n, int cap, int ntypes, const int *__restrict__ cnt,
+                                               const int *__restrict__ tcnt, const float *__restrict__ dist,
+                                               float lim, int *__restrict__ inner)
+{
+    int lane = threadIdx.x & 63;
+    int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;   // the whole wave
+    const float *d = dist + (long)i * cap;
+    int c0 = 0;
+    for (int ty = 0; ty < ntypes; ty++) {
+        int ct = tcnt ? tcnt[(long)i * kMaxTypes + ty] : cnt[i];
+        int m = 0;
+        for (int b = 0; b < ct; b += 64) m += __popcll(__ballot(b + lane < ct && d[c0 + b + lane] <= lim));
+        if (lane == 0) inner[(long)i * kMaxTypes + ty] = m;
+        c0 += ct;
+    }
+}
+
+// Largest |x_i - x0_i|: per block a maximum, then one atomicMax on the bits
+// (non-negative doubles order as their unsigned bit patterns).
+__global__ void __launch_bounds__(256) k_displacement(int n, const double *__restrict__ x,
+                                                      const double *__restrict__ x0,
+                                                      unsigned long long *__restrict__ disp)
+{
+    __shared__ double wmax[4];
+    int i = blockIdx.x * 256 + threadIdx.x;
+    double d = 0;
+    if (i < n) {
+        double d0 = x[3 * i] - x0[3 * i], d1 = x[3 * i + 1] - x0[3 * i + 1], d2 = x[3 * i + 2] - x0[3 * i + 2];
+        d = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        if (d != d) d = __builtin_huge_val();   // a NaN position turns the early end off
+    }
+    for (int off = 32; off > 0; off >>= 1) d = fmax(d, __shfl_xor(d, off));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+        if (m > 0) atomicMax(disp, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
 }  // namespace
+
+void launch_displacement(const dp_nlist *nl, int n, const double *x, hipStream_t st)
+{
+    if (!nl->x0 || n <= 0) return;
+    launch_fill_zero_int(reinterpret_cast<int *>(nl->disp), 2, st);
+    hipLaunchKernelGGL(k_displacement, dim3(div_up(n, 256)), dim3(256), 0, st, n, x, nl->x0, nl->disp);
+}
 
 void launch_fill_zero_int(int *p, long n, hipStream_t st)
 {
     if (n > 0) hipLaunchKernelGGL(k_zero_int, dim3(div_up(n, 256)), dim3(256), 0, st, p, n);
+}
+
+// The positions of the build and each atom's candidate prefixes within
+// rcut + margin (lists that carry them).
+static dp_status launch_prefix(const dp_model *m, dp_nlist *nl, const double *x, hipStream_t st)
+{
+    if (!nl->x0) return DP_OK;
+    int n = nl->natoms;
+    DP_HIP(hipMemcpyAsync(nl->x0, x, sizeof(double) * 3 * (size_t)n, hipMemcpyDeviceToDevice, st));
+    const bool typed = nl->ntypes > 1;
+    hipLaunchKernelGGL(k_inner, dim3(div_up(n, 4)), dim3(256), 0, st, n, nl->cap, typed ? nl->ntypes : 1, nl->cnt,
+                       typed ? nl->tcnt : nullptr, nl->dist, (float)(m->cfg.rcut + nl->margin), nl->inner);
+    return DP_OK;
 }
 
 dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, const int *types,
@@ -248,7 +311,6 @@ dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, c
     int cap2 = 1;
     while (cap2 < nl->cap) cap2 <<= 1;
     size_t lds = sizeof(unsigned long long) * cap2;
-    (void)m;
     // several types: the list's own copy (checked by build_type_layout) groups the candidates
     const bool typed = nl->ntypes > 1;
     const int *check = typed ? nullptr : types;
@@ -259,7 +321,7 @@ dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, c
         hipLaunchKernelGGL(k_candidates_open, dim3(xcd_grid(n)), dim3(64), lds, st, n, x, check, ktypes, rcs2,
                            nl->cap, nl->cnt, nl->nei, nl->shift, nl->dist, tcnt, nl->flags, 0);
         launch_reverse(nl, 0, n, st);
-        return DP_OK;
+        return launch_prefix(m, nl, x, st);
     }
     long ncell = (long)nl->nc[0] * nl->nc[1] * nl->nc[2];
     launch_fill_zero_int(nl->cell_cnt, ncell, st);
@@ -279,7 +341,7 @@ dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, c
                        nl->cell_cnt, nl->cell_atoms, rcs2, nl->cap, ktypes, nl->cnt, nl->nei, nl->shift,
                        nl->dist, tcnt, nl->flags, 0);
     launch_reverse(nl, 0, n, st);
-    return DP_OK;
+    return launch_prefix(m, nl, x, st);
 }
 
 dp_status launch_build_nlist_range(dp_nlist *nl, const double *x, int off, int n, const double *L,

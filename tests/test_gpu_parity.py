@@ -304,3 +304,37 @@ def test_forces_deterministic(P, model, precision):
     np.testing.assert_array_equal(a["F"], b["F"])
     np.testing.assert_array_equal(a["W"], b["W"])
     assert a["E"][0] == b["E"][0]
+
+
+@pytest.mark.parametrize("move", ["small", "large"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_moved_atoms_against_list_of_build(P, model, otab, cu_cfg, cu_params, precision, move):
+    """A list built at x, evaluated at moved positions.  Small moves (largest
+    0.1-0.2 A, under a quarter of the 2 A skin per pair) take the early end of
+    the candidate scan; the large case moves atom a toward an atom b that
+    was 8.55-8.7 A away at build (past rcut + skin/4) to 7.9 A, inside rcut,
+    so the scan must reach past the prefix to find the pair."""
+    x, box = synth.copper(6, 0.05, 11)
+    n, Lb = len(x), box[0, 0]
+    xm = x + np.random.Generator(np.random.PCG64(5)).normal(0.0, 0.03, x.shape)
+    if move == "large":
+        xm = x.copy()
+        d = x[None, :64, :] - x[:, None, :]
+        d -= Lb * np.round(d / Lb)
+        r = np.linalg.norm(d, axis=2)
+        ib, ia = np.argwhere((r > 8.55) & (r < 8.7))[0]
+        u = x[ib] - x[ia]
+        u -= Lb * np.round(u / Lb)
+        xm[ia] += (np.linalg.norm(u) - 7.9) * u / np.linalg.norm(u)   # 0.65-0.8 A, to 7.9 A from b
+        v = xm[ib] - xm[ia]
+        assert np.linalg.norm(v - Lb * np.round(v / Lb)) < cu_cfg["rcut"]
+    print(f"moved atoms: n={n} precision={precision} move={move}", flush=True)
+    nl = P.NeighborList(model, dev(x), box, skin=2.0)
+    xd = dev(xm)
+    out = P.compute(model, nl, xd, precision=precision, atom_energy=True)
+    nn = P.descriptor(model, nl, xd, precision=precision)["nnei"]
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    ref = oracle.evaluate(cu_cfg, cu_params, xm, box, table=otab)
+    np.testing.assert_array_equal(nn.cpu().numpy(), ref["nnei"])
+    check_against(ref, got, precision, n)
