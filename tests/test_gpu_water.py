@@ -224,3 +224,34 @@ def test_water_autograd_matches_compute(P, model, otab, w_cfg, w_params, precisi
         ref = oracle.evaluate(w_cfg, w_params, x, box, table=otab, types=t)
         assert abs(float(E.item()) - ref["E"]) <= 1e-10 * abs(ref["E"])
         np.testing.assert_allclose(-g.cpu().numpy(), ref["F"], rtol=0, atol=1e-10 * np.max(np.abs(ref["F"])))
+
+
+@pytest.mark.parametrize("move", ["small", "large"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_water_moved_atoms_against_list_of_build(P, model, otab, w_cfg, w_params, precision, move):
+    """A two-type list built at x and evaluated at moved positions: small
+    moves keep every atom within skin/8 (each type run scanned up to its
+    prefix within rcut + skin/4 = 6.5 A); the large case moves atom a from
+    6.55-6.7 A of atom b to 5.9 A, inside rcut, so the full runs are read."""
+    x, t, box = synth.water(2, sigma=0.05)
+    n, Lb = len(x), box[0, 0]
+    xm = x + np.random.Generator(np.random.PCG64(12)).normal(0.0, 0.03, x.shape)
+    if move == "large":
+        xm = x.copy()
+        d = x[None, :64, :] - x[:, None, :]
+        d -= Lb * np.round(d / Lb)
+        r = np.linalg.norm(d, axis=2)
+        ib, ia = np.argwhere((r > 6.55) & (r < 6.7))[0]
+        u = x[ib] - x[ia]
+        u -= Lb * np.round(u / Lb)
+        xm[ia] += (np.linalg.norm(u) - 5.9) * u / np.linalg.norm(u)
+    print(f"water moved atoms: n={n} precision={precision} move={move}", flush=True)
+    nl = P.NeighborList(model, dev(x), box, skin=2.0, types=dev(t, torch.int32))
+    xd = dev(xm)
+    out = P.compute(model, nl, xd, precision=precision, atom_energy=True)
+    nn = P.descriptor(model, nl, xd, precision=precision)["nnei"]
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    ref = oracle.evaluate(w_cfg, w_params, xm, box, table=otab, types=t)
+    np.testing.assert_array_equal(nn.cpu().numpy(), ref["nnei"])
+    check(ref, got, precision, n)
