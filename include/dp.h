@@ -44,7 +44,8 @@ typedef enum {
     DP_ERR_CAPACITY = -4,    /* a neighbor-list or cell capacity was exceeded   */
     DP_ERR_UNSUPPORTED = -5, /* a valid request the library does not implement  */
     DP_ERR_STATE = -6,       /* call order violated (e.g. no table yet)         */
-    DP_ERR_NONFINITE = -7    /* a non-finite energy was produced                */
+    DP_ERR_NONFINITE = -7,   /* a non-finite energy, virial or coordinate       */
+    DP_ERR_SKIN = -8         /* an atom moved skin/2 or more since the list's build */
 } dp_status;
 
 typedef enum {
@@ -123,14 +124,22 @@ dp_status dp_model_destroy(dp_model *model);
 dp_status dp_tabulate(dp_model *model, double s_max, double stride, double tail_max,
                       double tail_stride, void *stream);
 
-/* Selects the tanh of the fitting net in the FP32 and mixed modes: 0 the
- * native tanh (default), 1 a second-order polynomial per interval of width
- * 1/128 on [0, 8) with the value and slope of tanh at the left node and its
- * value at the right node, odd extension, 1 beyond 8 (the tabulated tanh of
- * Sec. 3.5; its largest error, 2.3e-7, is the saturation at 8, and 2.4e-8
- * inside the range).  FP64 mode always uses tanh.  The table is built on
- * `stream` at the first call with tabulated = 1.  DP_ERR_ARG on other values. */
+/* Selects the tanh of the fitting net, in every precision: 0 the native
+ * tanh (default), 1 a second-order polynomial per interval of width 1/128 on
+ * [0, 8) with the value and slope of tanh at the left node and its value at
+ * the right node, odd extension, 1 beyond 8 (the tabulated tanh of Sec. 3.5;
+ * its largest error, 2.3e-7, is the saturation at 8, and 2.4e-8 inside the
+ * range).  The table is built on `stream` at the first call with
+ * tabulated = 1, in FP64 (read by the FP64 mode) and rounded to FP32 (read by
+ * the FP32 and mixed modes).  DP_ERR_ARG on other values. */
 dp_status dp_fitting_tanh(dp_model *model, int tabulated, void *stream);
+
+/* Copies the FP64 tanh table to the host: coef_h[4 k + q] (k < *n_int) is
+ * the coefficient of t^q (q < 3; q = 3 is 0) on [k/128, (k+1)/128), with t
+ * the offset from the interval's left node.  *n_int receives the interval
+ * count (1024); coef_h may be NULL to query it.  DP_ERR_STATE when the table
+ * has not been built.  Synchronises. */
+dp_status dp_tanh_table_download(dp_model *model, double *coef_h, int *n_int);
 
 /* Copies the FP64 tables to the host: coef_h[((type * n + theta) * M + eta)
  * * 6 + xi] is the coefficient of t^xi of column eta on interval theta of the
@@ -153,15 +162,22 @@ dp_status dp_table_download(dp_model *model, double *coef_h, int *n_int);
  * have all moved at most skin/8 - 5e-4 A since then scans only those (the
  * others are provably beyond rcut); any other evaluation scans every
  * candidate.  Results do not depend on which scan runs.
- * Synchronises once to check the capacity flags; DP_ERR_CAPACITY when an
- * atom has more than 1024 candidates, DP_ERR_ARG for a type out of range. */
+ * Synchronises to check the capacity flags: a crowded cell or an atom with
+ * more candidates than the list holds grows that capacity and builds again
+ * (up to three times); DP_ERR_CAPACITY when an atom has more than 1024
+ * candidates, DP_ERR_ARG for a type out of range or a non-finite
+ * coordinate. */
 dp_status dp_build_nlist(dp_model *model, int natoms, const double *coords_d, const int *types_d,
                          const double *box_h, double skin, dp_nlist **inout, void *stream);
 dp_status dp_nlist_destroy(dp_nlist *nlist);
 
 /* Energy, forces and virial of the configuration the list was built for, at
  * coordinates coords_d (natoms x 3), which may have moved by less than
- * skin / 2 since the build.  Neighbors beyond rcut are skipped; when more
+ * skin / 2 since the build (more than that may lose pairs within rcut: the
+ * evaluation sets a sticky flag that dp_nlist_check reports as DP_ERR_SKIN;
+ * a non-finite energy, virial or coordinate is reported as
+ * DP_ERR_NONFINITE).  The model's rcut must lie below the list's
+ * rcut + skin (DP_ERR_ARG).  Neighbors beyond rcut are skipped; when more
  * than sel remain, the sel nearest are kept (counted in dp_nlist_stats).
  * Outputs (device, FP64; NULL skips):
  *   energy_d[1]        E = sum_i E_i
@@ -213,15 +229,29 @@ dp_status dp_descriptor(dp_model *model, dp_nlist *nlist, int natoms, const doub
 dp_status dp_nlist_stats(dp_nlist *nlist, int *max_nei, int *n_sel_overflow, int *n_table_oob,
                          int *n_cap_overflow);
 
+/* Synchronises and returns what the evaluations on the list since its last
+ * build have flagged: DP_ERR_NONFINITE (a non-finite energy, virial or
+ * coordinate), DP_ERR_SKIN (an atom had moved skin/2 or more since the build,
+ * so pairs within rcut may have been missed), else DP_ERR_CAPACITY or
+ * DP_ERR_ARG for a failed build, else DP_OK.  The flags stay set until the
+ * next dp_build_nlist. */
+dp_status dp_nlist_check(dp_nlist *nlist);
+
 /* Velocity-Verlet NVE (the MD protocol of the physical-systems section):
  * nsteps of half kick, drift, [neighbor rebuild every rebuild_every steps],
  * force, half kick, all on `stream` in FP64 (positions x_d and velocities
  * v_d, natoms x 3, updated in place; A and A/fs).  mass_h (HOST, ntypes
  * values) is the mass of each type in amu, dt_fs in fs; types_d as for
  * dp_build_nlist.  thermo_d (device, nsteps+1 rows of 2 doubles: potential
- * and kinetic energy, row 0 = start) may be NULL.  The nlist is rebuilt at
- * the start (synchronising once), then every rebuild_every steps on the
- * stream.  Synchronises at the end to check the capacity flags. */
+ * and kinetic energy, row 0 = start) may be NULL.  The nlist is built at
+ * the start and rebuilt every rebuild_every steps; each build synchronises
+ * once to check the capacities (grown and built again on an overflow, as in
+ * dp_build_nlist) and what the evaluations since the previous build flagged.
+ * The run stops at the first such check that fails, returning
+ * DP_ERR_NONFINITE, DP_ERR_SKIN (an atom moved skin/2 or more between
+ * builds) or DP_ERR_CAPACITY; x_d and v_d then hold the state of that step.
+ * The same checks run at the end.  The list's counters (dp_nlist_stats)
+ * accumulate over the run. */
 dp_status dp_nve_run(dp_model *model, dp_nlist **nlist, int natoms, double *x_d, double *v_d,
                      const int *types_d, const double *box_h, const double *mass_h, double dt_fs,
                      int nsteps, int rebuild_every, double skin, int mode, int precision,

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libdp.so")
 
 DP_OK = 0
 STATUS = {0: "DP_OK", -1: "DP_ERR_ARG", -2: "DP_ERR_HIP", -3: "DP_ERR_OOM", -4: "DP_ERR_CAPACITY",
-          -5: "DP_ERR_UNSUPPORTED", -6: "DP_ERR_STATE", -7: "DP_ERR_NONFINITE"}
+          -5: "DP_ERR_UNSUPPORTED", -6: "DP_ERR_STATE", -7: "DP_ERR_NONFINITE", -8: "DP_ERR_SKIN"}
 FP64, FP32, MIXED_BF16 = 0, 1, 2
 COMPRESSED, PLAIN, TAB_UNFUSED, FUSED_PADDED, FUSED = 0, 1, 2, 3, 4
 
@@ -44,6 +44,7 @@ _SIG = {
     "dp_tabulate": [_vp, _d, _d, _d, _d, _vp],
     "dp_fitting_tanh": [_vp, _i, _vp],
     "dp_table_download": [_vp, _vp, _pi],
+    "dp_tanh_table_download": [_vp, _vp, _pi],
     "dp_build_nlist": [_vp, _i, _vp, _vp, _vp, _d, _pvp, _vp],
     "dp_nlist_destroy": [_vp],
     "dp_compute": [_vp, _vp, _i, _vp, _vp, _vp, _i, _i, _vp, _vp, _vp, _vp, _vp],
@@ -51,6 +52,7 @@ _SIG = {
     "dp_energy_forward": [_vp, _vp, _i, _vp, _i, _i, _vp, _vp, _vp],
     "dp_energy_backward": [_vp, _vp, _i, _vp, _i, _i, _vp, _vp, _vp],
     "dp_nlist_stats": [_vp, _pi, _pi, _pi, _pi],
+    "dp_nlist_check": [_vp],
     "dp_nve_run": [_vp, _pvp, _i, _vp, _vp, _vp, _vp, _vp, _d, _i, _i, _d, _i, _i, _vp, _vp],
     "dp_batch_create": [_vp, _i, _i, _d, _pvp],
     "dp_batch_destroy": [_vp],

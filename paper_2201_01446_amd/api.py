@@ -65,10 +65,19 @@ class Model:
         return self
 
     def fitting_tanh(self, tabulated=True):
-        """The fitting net's tanh in the FP32 and mixed modes: the second-order
-        table (True) or the native function (False)."""
+        """The fitting net's tanh in every precision: the second-order table
+        (True) or the native function (False)."""
         check(lib.dp_fitting_tanh(self.h, 1 if tabulated else 0, _stream()))
         return self
+
+    def tanh_table(self):
+        """FP64 coefficients [1024, 4] of the tabulated tanh (a0, a1, a2, 0 per
+        interval of width 1/128 on [0, 8))."""
+        n = ctypes.c_int()
+        check(lib.dp_tanh_table_download(self.h, None, ctypes.byref(n)))
+        out = np.zeros((n.value, 4))
+        check(lib.dp_tanh_table_download(self.h, out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
+        return out
 
     def table(self):
         """FP64 coefficients [ntypes * n_int, M, 6] (the types' tables back to back)."""
@@ -102,6 +111,12 @@ class NeighborList:
         self.box, self.skin, self.natoms = b, skin, n
         check(lib.dp_build_nlist(self.model.h, n, _ptr(coords), _ptr(types), bp, skin, ctypes.byref(self.h),
                                  _stream()))
+        return self
+
+    def check(self):
+        """Raises DPError for what the evaluations since the last build flagged
+        (DP_ERR_NONFINITE, DP_ERR_SKIN) or a capacity overflow of the build."""
+        check(lib.dp_nlist_check(self.h))
         return self
 
     def stats(self):

@@ -163,6 +163,7 @@ dp_status prepare_nlist(const dp_model *m, int natoms, const double *box, double
     DP_HIP(hipGetDevice(&dev));
     nl->device = dev;
     nl->rc_build = m->cfg.rcut + skin;
+    nl->rcut_build = m->cfg.rcut;
     double rcs = nl->rc_build;
     int cap;
     if (box) {
@@ -210,8 +211,10 @@ dp_status prepare_nlist(const dp_model *m, int natoms, const double *box, double
         cap = (int)round_up(natoms, 64);
     }
     if (cap < 128) cap = 128;
+    if (cap < nl->cap_floor) cap = nl->cap_floor;
     if (cap > kCapMax) cap = kCapMax;
-    bool grow = natoms > nl->alloc_atoms || cap > nl->cap;
+    bool grow_atoms = natoms > nl->alloc_atoms;
+    bool grow = grow_atoms || cap > nl->cap;
     const int T = m->cfg.ntypes;
     // a list serves models of one type count; a change reallocates the type arrays
     bool retype = T != nl->ntypes;
@@ -236,7 +239,9 @@ dp_status prepare_nlist(const dp_model *m, int natoms, const double *box, double
         nl->alloc_atoms = alloc;
         nl->cap = capn;
     }
-    if (grow || retype) {
+    // (the per-atom type arrays survive a capacity increase: a rebuild inside
+    // an MD run reuses the list's copy of the types)
+    if (grow_atoms || retype) {
         void *q[] = {nl->type, nl->tcnt, nl->row, nl->ratom, nl->tblk};
         for (void *v : q)
             if (v) DP_HIP(hipFree(v));
@@ -275,12 +280,42 @@ dp_status read_flags(dp_nlist *nl, int *f, hipStream_t st)
 
 dp_status check_build_flags(const int *f)
 {
+    if (f[kFlagBadCoord]) return fail(DP_ERR_ARG, "a coordinate is not finite");
     if (f[kFlagBadType]) return fail(DP_ERR_ARG, "an atom type lies outside [0, ntypes)");
     if (f[kFlagCapOverflow])
         return fail(DP_ERR_CAPACITY, "an atom has more skin candidates than the list capacity "
                                      "(or coordinates lie more than 60 boxes away)");
     if (f[kFlagCellOverflow]) return fail(DP_ERR_CAPACITY, "a cell holds more atoms than its capacity");
     return DP_OK;
+}
+
+// Conditions the evaluations since the last build have flagged.
+dp_status check_eval_flags(const int *f)
+{
+    if (f[kFlagBadCoord]) return fail(DP_ERR_NONFINITE, "a coordinate became non-finite");
+    if (f[kFlagNonFinite]) return fail(DP_ERR_NONFINITE, "an energy or virial was not finite");
+    if (f[kFlagSkin])
+        return fail(DP_ERR_SKIN, "an atom moved half the skin or more since the neighbor list was built, so "
+                                 "pairs within rcut may be missing: rebuild more often or use a wider skin");
+    return DP_OK;
+}
+
+// Capacity failures of a build that another attempt with larger capacities
+// can cure: a crowded cell doubles the cell capacity, a truncated candidate
+// list doubles the candidate capacity (up to kCapMax).  True when it grew one.
+bool grow_after_overflow(dp_nlist *nl, const int *f)
+{
+    if (f[kFlagBadType] || f[kFlagBadCoord]) return false;
+    bool grew = false;
+    if (f[kFlagCellOverflow]) {
+        nl->cellcap *= 2;
+        grew = true;
+    }
+    if (f[kFlagCapOverflow] && nl->cap < kCapMax) {
+        nl->cap_floor = (int)std::min<long>(kCapMax, round_up(2L * nl->cap, 64));
+        grew = true;
+    }
+    return grew;
 }
 
 dp_status check_compute_args(const dp_model *m, const dp_nlist *nl, int natoms, const double *x, int mode,
@@ -292,6 +327,8 @@ dp_status check_compute_args(const dp_model *m, const dp_nlist *nl, int natoms, 
     if (precision < DP_FP64 || precision > DP_MIXED_BF16) return fail(DP_ERR_ARG, "unknown precision");
     if (mode != DP_PLAIN && !m->tab64) return fail(DP_ERR_STATE, "dp_tabulate has not run");
     if (nl->ntypes != m->cfg.ntypes) return fail(DP_ERR_ARG, "the list was built for a model of another type count");
+    if (m->cfg.rcut >= nl->rc_build)
+        return fail(DP_ERR_ARG, "the model's rcut reaches past the list's rcut + skin");
     if (m->cfg.ntypes > 1 && (mode == DP_PLAIN || mode == DP_TAB_UNFUSED))
         return fail(DP_ERR_UNSUPPORTED, "several atom types need a fused mode (0, 3 or 4)");
     return DP_OK;
@@ -431,7 +468,8 @@ dp_status dp_model_create(const dp_model_config *cfg, const double *params_h, si
 dp_status dp_model_destroy(dp_model *m)
 {
     if (!m) return DP_OK;
-    void *p[] = {m->emb_d, m->fitb_d, m->fitb_f, m->tab64, m->tab32, m->nodes, m->embg64, m->embg32, m->tanh_tab};
+    void *p[] = {m->emb_d, m->fitb_d, m->fitb_f, m->tab64, m->tab32, m->nodes, m->embg64, m->embg32, m->tanh_tab,
+                 m->tanh_tab64};
     for (void *q : p)
         if (q) (void)hipFree(q);
     free_fit(m->w64);
@@ -487,11 +525,23 @@ dp_status dp_fitting_tanh(dp_model *m, int tabulated, void *stream)
     if (!m || (tabulated != 0 && tabulated != 1)) return fail(DP_ERR_ARG, "bad argument");
     if (tabulated && !m->tanh_tab) {
         DP_HIP(hipMalloc(&m->tanh_tab, sizeof(float) * 4 * kTanhN));
-        launch_tanh_table(m->tanh_tab, (hipStream_t)stream);
+        DP_HIP(hipMalloc(&m->tanh_tab64, sizeof(double) * 4 * kTanhN));
+        launch_tanh_table(m->tanh_tab64, m->tanh_tab, (hipStream_t)stream);
         dp_status s = step_check("tanh_table", (hipStream_t)stream);
         if (s != DP_OK) return s;
     }
     m->tanh_on = tabulated;
+    return DP_OK;
+}
+
+dp_status dp_tanh_table_download(dp_model *m, double *coef_h, int *n_int)
+{
+    if (!m) return fail(DP_ERR_ARG, "NULL model");
+    if (n_int) *n_int = kTanhN;
+    if (!coef_h) return DP_OK;
+    if (!m->tanh_tab64) return fail(DP_ERR_STATE, "the tanh table has not been built (dp_fitting_tanh)");
+    DP_HIP(hipDeviceSynchronize());
+    DP_HIP(hipMemcpy(coef_h, m->tanh_tab64, sizeof(double) * 4 * kTanhN, hipMemcpyDeviceToHost));
     return DP_OK;
 }
 
@@ -522,10 +572,7 @@ dp_status dp_build_nlist(dp_model *m, int natoms, const double *coords_d, const 
         if ((s = step_check("build_nlist", st)) != DP_OK) return s;
         int f[kNumFlags];
         if ((s = read_flags(nl, f, st)) != DP_OK) return s;
-        if (f[kFlagCellOverflow] && !f[kFlagBadType] && attempt < 3) {
-            nl->cellcap *= 2;   // a crowded cell: retry with room to spare
-            continue;
-        }
+        if (attempt < 3 && grow_after_overflow(nl, f)) continue;   // retry with room to spare
         return check_build_flags(f);
     }
     return fail(DP_ERR_CAPACITY, "cell capacity");
@@ -633,12 +680,20 @@ dp_status dp_nve_run(dp_model *m, dp_nlist **nlp, int natoms, double *x, double 
     if (!(dt_fs > 0) || nsteps < 0 || rebuild_every < 1)
         return fail(DP_ERR_ARG, "need dt > 0, nsteps >= 0, rebuild_every >= 1");
     hipStream_t st = (hipStream_t)stream;
-    dp_status s = prepare_nlist(m, natoms, box_h, skin, nlp);
-    if (s != DP_OK) return s;
-    dp_nlist *nl = *nlp;
-    if ((s = check_compute_args(m, nl, natoms, x, mode, precision)) != DP_OK) return s;
-    if ((s = build_all(m, nl, x, types, st)) != DP_OK) return s;
-    if ((s = step_check("build_nlist", st)) != DP_OK) return s;
+    dp_status s;
+    dp_nlist *nl = nullptr;
+    for (int attempt = 0;; attempt++) {   // the first build, checked as in dp_build_nlist
+        if ((s = prepare_nlist(m, natoms, box_h, skin, nlp)) != DP_OK) return s;
+        nl = *nlp;
+        if ((s = check_compute_args(m, nl, natoms, x, mode, precision)) != DP_OK) return s;
+        if ((s = build_all(m, nl, x, types, st)) != DP_OK) return s;
+        if ((s = step_check("build_nlist", st)) != DP_OK) return s;
+        int f[kNumFlags];
+        if ((s = read_flags(nl, f, st)) != DP_OK) return s;
+        if (attempt < 3 && grow_after_overflow(nl, f)) continue;
+        if ((s = check_build_flags(f)) != DP_OK) return s;
+        break;
+    }
     // rebuilds inside the run reuse the list's copy of the types
     const int *tl = T > 1 ? nl->type : types;
     const int *tk = T > 1 ? nl->type : nullptr;   // per-atom type of the Verlet kernels
@@ -654,9 +709,26 @@ dp_status dp_nve_run(dp_model *m, dp_nlist **nlp, int natoms, double *x, double 
     for (int step = 1; step <= nsteps; step++) {
         launch_verlet_kick_drift(x, v, F, natoms, tk, kick, dt_fs, st);
         if (step % rebuild_every == 0) {
-            DP_TIMED("nlist", st, s = launch_build_nlist(m, nl, x, tl, false, st));
-            if (s != DP_OK) return s;
-            if ((s = step_check("build_nlist", st)) != DP_OK) return s;
+            // The counters of the run accumulate (no reset).  One
+            // synchronisation per rebuild checks what the evaluations since the
+            // last one flagged, and the build's capacities (grown and built
+            // again on an overflow, as in dp_build_nlist).
+            for (int attempt = 0;; attempt++) {
+                DP_TIMED("nlist", st, s = launch_build_nlist(m, nl, x, tl, false, st));
+                if (s != DP_OK) return s;
+                if ((s = step_check("build_nlist", st)) != DP_OK) return s;
+                int f[kNumFlags];
+                if ((s = read_flags(nl, f, st)) != DP_OK) return s;
+                if ((s = check_eval_flags(f)) != DP_OK) return s;
+                if (attempt < 3 && grow_after_overflow(nl, f)) {
+                    launch_fill_zero_int(nl->flags + kFlagCapOverflow, 1, st);
+                    launch_fill_zero_int(nl->flags + kFlagCellOverflow, 1, st);
+                    if ((s = prepare_nlist(m, natoms, box_h, skin, nlp)) != DP_OK) return s;
+                    continue;
+                }
+                if ((s = check_build_flags(f)) != DP_OK) return s;
+                break;
+            }
         }
         s = compute_common(m, nl, natoms, x, mode, precision, E, F, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, st);
         if (s != DP_OK) return s;
@@ -666,7 +738,18 @@ dp_status dp_nve_run(dp_model *m, dp_nlist **nlp, int natoms, double *x, double 
     }
     int f[kNumFlags];
     if ((s = read_flags(nl, f, st)) != DP_OK) return s;
+    if ((s = check_eval_flags(f)) != DP_OK) return s;
     return check_build_flags(f);
+}
+
+dp_status dp_nlist_check(dp_nlist *nl)
+{
+    if (!nl) return fail(DP_ERR_ARG, "NULL list");
+    int f[kNumFlags];
+    DP_HIP(hipDeviceSynchronize());
+    DP_HIP(hipMemcpy(f, nl->flags, sizeof(f), hipMemcpyDeviceToHost));
+    dp_status s = check_eval_flags(f);
+    return s != DP_OK ? s : check_build_flags(f);
 }
 
 dp_status dp_footprint_bytes(const dp_model *m, int natoms, size_t *bytes)
@@ -694,6 +777,7 @@ dp_status dp_batch_create(dp_model *m, int max_atoms, int max_requests, double s
     b->nl = nl;
     DP_HIP(hipGetDevice(&nl->device));
     nl->rc_build = m->cfg.rcut + skin;
+    nl->rcut_build = m->cfg.rcut;
     nl->periodic = true;
     nl->cap = kCapMax;
     nl->alloc_atoms = max_atoms;

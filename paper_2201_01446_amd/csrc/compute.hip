@@ -124,7 +124,8 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
     }
     for (int t = 0; t < kMaxTypes; t++) rt.b4[t] = m->b4[t];
     bool fwd = a.phase != 2, bwd = a.need_forces && a.phase != 1;
-    launch_displacement(nl, n, a.x, st);   // decides the early end of the candidate scans
+    // decides the early end of the candidate scans, and flags moves beyond the list's reach
+    launch_displacement(nl, n, a.x, nl->rc_build - m->cfg.rcut, st);
     if (fwd) {
         if (PLAIN) {
             bool tab = a.mode == DP_TAB_UNFUSED;
@@ -139,8 +140,9 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
         }
         if (a.T_out) launch_to_double<TR>((long)n * 4 * kM, (const TR *)w.T, a.T_out, st);
         if (a.D_out) launch_op_to_double<TA>(n, kDdim, (const TA *)w.D, typed ? nl->row : nullptr, a.D_out, st);
-        // the fitting net's tanh: native, or tabulated in the FP32 and mixed modes when enabled
-        const float *ttab = (a.precision != DP_FP64 && m->tanh_on) ? m->tanh_tab : nullptr;
+        // the fitting net's tanh: native, or the table (in the epilogue's precision) when enabled
+        const float *ttab = m->tanh_on ? m->tanh_tab : nullptr;
+        const double *ttab64 = m->tanh_on ? m->tanh_tab64 : nullptr;
         // when the operand type is the result type (FP32, FP64) the next
         // layer reads the result array itself; BF16 needs the split copy
         constexpr bool same = std::is_same<TA, TR>::value;
@@ -148,14 +150,17 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
         const TA *y1in = (const TA *)(same ? w.y1r : w.y1o), *y2in = (const TA *)(same ? w.y2r : w.y2o);
         e = Epi{c1, nullptr, nullptr, nullptr, w.y1r, y1op, nullptr};
         e.tanh_tab = ttab;
+        e.tanh_tab64 = ttab64;
         e = grouped(e, kFitPad, ks * kDdim);
         DP_TIMED("fit_fwd1", st, launch_gemm<TA, TR>(EPI_T1, mr, kFitPad, ks * kDdim, (const TA *)w.D, (const TA *)fw.V1t, e, st));
         e = Epi{c2, w.y1r, nullptr, nullptr, w.y2r, y2op, w.t2r};
         e.tanh_tab = ttab;
+        e.tanh_tab64 = ttab64;
         e = grouped(e, kFitPad, ks * kFitPad);
         DP_TIMED("fit_fwd2", st, launch_gemm<TA, TR>(EPI_T2, mr, kFitPad, ks * kFitPad, y1in, (const TA *)fw.V2t, e, st));
         e = Epi{c3, nullptr, nullptr, nullptr, nullptr, nullptr, w.t3r};
         e.tanh_tab = ttab;
+        e.tanh_tab64 = ttab64;
         e = grouped(e, kFitPad, ks * kFitPad);
         DP_TIMED("fit_fwd3", st, launch_gemm<TA, TR>(EPI_T3, mr, kFitPad, ks * kFitPad, y2in, (const TA *)fw.V3t, e, st));
     }
@@ -191,9 +196,9 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
     double *energy = a.phase == 2 ? nullptr : a.energy;
     double *virial = bwd ? a.virial : nullptr;
     if (a.nseg > 0)
-        launch_segment_reduce(a.nseg, a.seg_off, w.e_atom, bwd ? w.w_atom : nullptr, energy, virial, st);
-    else if (energy || virial)
-        launch_reduce(n, w.e_atom, bwd ? w.w_atom : nullptr, w.part, energy, virial, st);
+        launch_segment_reduce(a.nseg, a.seg_off, w.e_atom, bwd ? w.w_atom : nullptr, energy, virial, nl->flags, st);
+    else
+        launch_reduce(n, w.e_atom, bwd ? w.w_atom : nullptr, w.part, energy, virial, nl->flags, st);
     if (a.atom_energy && a.phase != 2)
         DP_HIP(hipMemcpyAsync(a.atom_energy, w.e_atom, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     return step_check("reduce", st);

@@ -33,7 +33,10 @@ enum Flag {
     kFlagCapOverflow = 3 * kFlagStride,   // atoms whose candidate list hit cap
     kFlagCellOverflow = 4 * kFlagStride,  // atoms that did not fit their cell
     kFlagBadType = 5 * kFlagStride,       // atoms with a type outside [0, ntypes)
-    kNumFlags = 8 * kFlagStride
+    kFlagSkin = 6 * kFlagStride,          // an evaluation found an atom moved too far since the build
+    kFlagNonFinite = 7 * kFlagStride,     // an evaluation produced a non-finite energy or virial
+    kFlagBadCoord = 8 * kFlagStride,      // a non-finite coordinate was seen
+    kNumFlags = 12 * kFlagStride
 };
 
 struct TableInfo {
@@ -71,9 +74,10 @@ struct dp_model {
     double *tab64 = nullptr;     // [ntypes * n_int][M][6]: type t's table at interval t * n_int
     float *tab32 = nullptr;      // [ntypes * n_int][M][6]
     double *nodes = nullptr;     // scratch [ntypes][n_int+1][M][3] of node values g, g', g''
-    // tanh of the fitting net in the FP32 and mixed modes: native, or the
-    // second-order table [kTanhN][a0, a1, a2, 0] on [0, 8)
+    // tanh of the fitting net: native, or the second-order table
+    // [kTanhN][a0, a1, a2, 0] on [0, 8), in FP64 (FP64 epilogues) and FP32
     float *tanh_tab = nullptr;
+    double *tanh_tab64 = nullptr;
     int tanh_on = 0;
 };
 
@@ -110,6 +114,10 @@ struct dp_nlist {
     int *inner = nullptr;                 // [natoms * kMaxTypes]
     unsigned long long *disp = nullptr;   // [1]
     double margin = 0;                    // skin / 4
+    // the model cut-off the list was built for (rc_build = rcut_build + skin),
+    // and a lower bound on the candidate capacity (raised after an overflow)
+    double rcut_build = 0;
+    int cap_floor = 0;
     // several types: each atom's type, its candidates per type (the list is
     // grouped by type), and the fitting net's row of each atom: rows are
     // grouped by center type, group t at [trow[t], trow[t + 1]), each group
@@ -209,11 +217,14 @@ __device__ inline int xcd_item(int b, int grid) { return (b % kXcd) * (grid / kX
 void launch_fill_zero(double *p, long n, hipStream_t st);
 void launch_fill_zero_bytes(void *p, size_t nbytes, hipStream_t st);
 void launch_fill_zero_int(int *p, long n, hipStream_t st);
-// The largest |x_i - x0_i| into nl->disp (no-op for lists without x0).
-void launch_displacement(const dp_nlist *nl, int n, const double *x, hipStream_t st);
+// The largest |x_i - x0_i| into nl->disp (no-op for lists without x0); sets
+// kFlagSkin when twice it reaches `lim` (the list's reach beyond the
+// evaluating model's cut-off: a pair within that cut-off may then lack its
+// candidate) and kFlagBadCoord on a non-finite position.
+void launch_displacement(const dp_nlist *nl, int n, const double *x, double lim, hipStream_t st);
 dp_status launch_tabulate(dp_model *m, hipStream_t st);
 constexpr int kTanhN = 1024;   // tanh table intervals of width 1/128 on [0, 8)
-void launch_tanh_table(float *tab, hipStream_t st);
+void launch_tanh_table(double *tab64, float *tab32, hipStream_t st);
 dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, const int *types,
                              bool reset_flags, hipStream_t st);
 // Candidates of the atoms [off, off + n) of a batch, all inside one cell with
@@ -221,7 +232,7 @@ dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, c
 dp_status launch_build_nlist_range(dp_nlist *nl, const double *x, int off, int n, const double *L,
                                    hipStream_t st);
 void launch_segment_reduce(int nreq, const int *offsets, const double *e_atom, const double *w_atom,
-                           double *energy, double *virial, hipStream_t st);
+                           double *energy, double *virial, int *flags, hipStream_t st);
 void launch_expand_boxes(int nreq, const int *offsets, const double *Lreq, double *atomL, hipStream_t st);
 
 // BF16 operands of the fitting net are kept as an exact-ish split
@@ -254,7 +265,8 @@ struct Epi {
     void *out_t;       // TR[M][N]
     int resw = 0;      // EPI_EMB: width of the residual input
     int half = 0;      // EPI_FOLD
-    const float *tanh_tab = nullptr;   // FP32 epilogues: tanh from this table (kTanhN x 4), or native
+    const float *tanh_tab = nullptr;     // FP32 epilogues: tanh from this table (kTanhN x 4), or native
+    const double *tanh_tab64 = nullptr;  // FP64 epilogues: the same table in FP64, or native
     // rows grouped by type (several types): a tile whose first row lies in
     // [trow[t], trow[t + 1]) takes Bt + t bstride and bias / resv + t vstride
     int ntr = 0;
@@ -278,8 +290,10 @@ void launch_energy(int rows, const TR *y2, const TR *t3, const TR *w4, const Row
                    TA *dz3, hipStream_t st);
 template <typename TR>
 void launch_dT(int n, const TR *dD, const TR *T, TR *dT, hipStream_t st);
+// E = sum E_i and W = sum W_i in a fixed order; kFlagNonFinite when either
+// is not finite.
 void launch_reduce(int n, const double *e_atom, const double *w_atom, double *part, double *energy,
-                   double *virial, hipStream_t st);
+                   double *virial, int *flags, hipStream_t st);
 template <typename T>
 void launch_to_double(long n, const T *a, double *b, hipStream_t st);
 // GEMM operand matrix (n atoms, ncols logical columns) to FP64 (hi + lo for

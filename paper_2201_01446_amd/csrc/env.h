@@ -134,6 +134,15 @@ __device__ inline void env_geom(const EnvArgs &A, const V4<real> &d, real &rinv,
 
 __device__ inline int s8(int v, int sh) { return (int)(signed char)((v >> sh) & 0xFF); }
 
+// Rank of an image shift among equal distances to the same atom j: the
+// signed components compared in the order x, y, z (so (-1,0,0) precedes
+// (0,-1,0), which precedes (0,0,1)).  Returned as one integer that orders
+// like that lexicographic comparison.
+__device__ inline int shift_order(int s)
+{
+    return ((s8(s, 0) + 128) << 16) | ((s8(s, 8) + 128) << 8) | (s8(s, 16) + 128);
+}
+
 // Table interval of s (left-closed) and the offset t from its left node;
 // returns 1 when s lies past the table end: then s is clamped there (G is
 // constant, G' = 0) and bit 30 of th tells the backward to drop G'.
@@ -268,19 +277,21 @@ __device__ int scan_candidates(int i, const EnvArgs &A, NbrLDS<real> L, int lane
         }
     }
     if (n_in > lim) {
-        // keep the lim nearest by (r^2, j, image); ranks are a permutation
+        // keep the lim nearest by (r^2, j, image shift x, y, z); ranks are a
+        // permutation
         for (int k = c0 + lane; k < c0 + ct; k += 64) {
             int j = nei[k], s = shf[k];
             double d0, d1, d2;
             if (!within_cut(A.x, j, xi0, xi1, xi2, s, L0, L1, L2, A.rc2, d0, d1, d2)) continue;
             double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+            int so = shift_order(s);
             int rank = 0;
             for (int q = c0; q < c0 + ct; q++) {
                 int jq = nei[q], sq = shf[q];
                 double e0, e1, e2;
                 if (!within_cut(A.x, jq, xi0, xi1, xi2, sq, L0, L1, L2, A.rc2, e0, e1, e2)) continue;
                 double rq = e0 * e0 + e1 * e1 + e2 * e2;
-                bool less = rq < r2 || (rq == r2 && (jq < j || (jq == j && sq < s)));
+                bool less = rq < r2 || (rq == r2 && (jq < j || (jq == j && shift_order(sq) < so)));
                 rank += less ? 1 : 0;
             }
             if (rank < lim) {
@@ -443,7 +454,8 @@ inline EnvArgs make_env_args(const dp_model *m, const dp_nlist *nl, const double
     for (int t = 0; t < kMaxTypes; t++) A.sel_t[t] = t < m->cfg.ntypes ? m->cfg.sel_t[t] : 0;
     A.tcnt = nl->ntypes > 1 ? nl->tcnt : nullptr;
     A.n_int = m->tab.n_int();
-    A.inner = nl->x0 ? nl->inner : nullptr;
+    // the prefixes were taken at the build's cut-off: another model's reads everything
+    A.inner = (nl->x0 && m->cfg.rcut == nl->rcut_build) ? nl->inner : nullptr;
     A.disp = nl->disp;
     A.margin = nl->margin;
     A.row = nl->ntypes > 1 ? nl->row : nullptr;

@@ -80,8 +80,8 @@ template <> __device__ inline __bf16 tod<__bf16>(double v) { return (__bf16)(flo
 __device__ inline float tanh_r(float v) { return tanhf(v); }
 __device__ inline double tanh_r(double v) { return tanh(v); }
 
-// tanh of an FP32 epilogue: native, or from the second-order table on
-// [0, 8) (odd extension, 1 beyond 8); FP64 epilogues always take tanh.
+// tanh of an epilogue: native, or from the second-order table on [0, 8)
+// (odd extension, 1 beyond 8), read in the epilogue's precision.
 __device__ inline float tanh_e(float x, const float *tab)
 {
     if (!tab) return tanhf(x);
@@ -94,7 +94,21 @@ __device__ inline float tanh_e(float x, const float *tab)
     float y = fmaf(t, fmaf(t, a.z, a.y), a.x);
     return copysignf(y, x);
 }
-__device__ inline double tanh_e(double x, const float *) { return tanh(x); }
+__device__ inline double tanh_e(double x, const double *tab)
+{
+    if (!tab) return tanh(x);
+    double ax = fabs(x);
+    if (ax >= 8.0) return copysign(1.0, x);
+    int k = (int)(ax * (kTanhN / 8.0));
+    k = k < kTanhN - 1 ? k : kTanhN - 1;
+    double t = ax - k * (8.0 / kTanhN);
+    const double *a = tab + 4 * k;
+    double y = fma(t, fma(t, a[2], a[1]), a[0]);
+    return copysign(y, x);
+}
+// The table an epilogue of result type TR takes (NULL: native tanh).
+__device__ inline const float *tanh_table_for(const Epi &e, float) { return e.tanh_tab; }
+__device__ inline const double *tanh_table_for(const Epi &e, double) { return e.tanh_tab64; }
 
 }  // namespace
 
@@ -320,17 +334,17 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const TA *
                 if constexpr (EPI == EPI_LIN) {
                     ((TR *)e.out_r)[idx] = v;
                 } else if constexpr (EPI == EPI_T1) {
-                    TR y = tanh_e(v + bias[gn], e.tanh_tab);
+                    TR y = tanh_e(v + bias[gn], tanh_table_for(e, TR()));
                     ((TR *)e.out_r)[idx] = y;
                     if (e.out_o) store_op((TA *)e.out_o, gm, gn, N, (double)y);
                 } else if constexpr (EPI == EPI_T2) {
-                    TR t = tanh_e(v + bias[gn], e.tanh_tab);
+                    TR t = tanh_e(v + bias[gn], tanh_table_for(e, TR()));
                     TR y = ((const TR *)e.res)[idx] + t;
                     ((TR *)e.out_t)[idx] = t;
                     ((TR *)e.out_r)[idx] = y;
                     if (e.out_o) store_op((TA *)e.out_o, gm, gn, N, (double)y);
                 } else if constexpr (EPI == EPI_T3) {
-                    ((TR *)e.out_t)[idx] = tanh_e(v + bias[gn], e.tanh_tab);
+                    ((TR *)e.out_t)[idx] = tanh_e(v + bias[gn], tanh_table_for(e, TR()));
                 } else if constexpr (EPI == EPI_EMB) {
                     TR t = tanh_r(v + bias[gn]);
                     ((TR *)e.out_t)[idx] = t;
@@ -455,7 +469,7 @@ __global__ void __launch_bounds__(256) k_reduce_partial(int n, const double *__r
 // Sum of the kRedBlocks partials: one per thread, then a tree in LDS
 // (a fixed order).
 __global__ void __launch_bounds__(256) k_reduce_final(int nblk, const double *__restrict__ part,
-                                                      double *energy, double *virial)
+                                                      double *energy, double *virial, int *flags)
 {
     __shared__ double sh[256][11];
     int t = threadIdx.x;
@@ -468,6 +482,7 @@ __global__ void __launch_bounds__(256) k_reduce_final(int nblk, const double *__
     }
     if (t == 0 && energy) *energy = sh[0][0];
     if (t >= 1 && t < 10 && virial) virial[t - 1] = sh[0][t];
+    if (t < 10 && !isfinite(sh[0][t])) atomicOr(&flags[kFlagNonFinite], 1);
 }
 
 template <typename T>
@@ -562,11 +577,11 @@ template void launch_dT<double>(int, const double *, const double *, double *, h
 template void launch_dT<float>(int, const float *, const float *, float *, hipStream_t);
 
 void launch_reduce(int n, const double *e_atom, const double *w_atom, double *part, double *energy,
-                   double *virial, hipStream_t st)
+                   double *virial, int *flags, hipStream_t st)
 {
     hipLaunchKernelGGL(k_reduce_partial, dim3(kRedBlocks), dim3(256), 0, st, n, e_atom, w_atom, part);
     static_assert(kRedBlocks <= 256, "one partial per thread");
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, kRedBlocks, part, energy, virial);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, kRedBlocks, part, energy, virial, flags);
 }
 
 template <typename T>

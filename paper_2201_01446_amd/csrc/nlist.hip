@@ -59,6 +59,7 @@ __global__ void k_bin(int n, const double *__restrict__ x, const int *__restrict
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (types && types[i] != 0) atomicAdd(&flags[kFlagBadType], 1);   // one-type lists only
+    if (!isfinite(x[3 * i]) || !isfinite(x[3 * i + 1]) || !isfinite(x[3 * i + 2])) atomicOr(&flags[kFlagBadCoord], 1);
     double L[3] = {Lx, Ly, Lz};
     int nc[3] = {ncx, ncy, ncz};
     int k[3], c[3];
@@ -215,6 +216,8 @@ __global__ void __launch_bounds__(64) k_candidates_open(int n, const double *__r
     if (lane == 0) {
         count = 0;
         if (check_types && check_types[i] != 0) atomicAdd(&flags[kFlagBadType], 1);
+        if (!isfinite(x[3 * i]) || !isfinite(x[3 * i + 1]) || !isfinite(x[3 * i + 2]))
+            atomicOr(&flags[kFlagBadCoord], 1);
     }
     __syncthreads();
     double xi0 = x[3 * i], xi1 = x[3 * i + 1], xi2 = x[3 * i + 2];
@@ -254,34 +257,44 @@ __global__ void __launch_bounds__(256) k_inner(int n, int cap, int ntypes, const
 
 // Largest |x_i - x0_i|: per block a maximum, then one atomicMax on the bits
 // (non-negative doubles order as their unsigned bit patterns).
+// A block whose largest displacement d has 2 d >= lim (and d > 0) sets the
+// skin flag: a pair now within the evaluating cut-off may have been beyond
+// the list's reach at build.  A non-finite position counts as infinitely far
+// and also sets the coordinate flag.
 __global__ void __launch_bounds__(256) k_displacement(int n, const double *__restrict__ x,
-                                                      const double *__restrict__ x0,
-                                                      unsigned long long *__restrict__ disp)
+                                                      const double *__restrict__ x0, double lim,
+                                                      unsigned long long *__restrict__ disp,
+                                                      int *__restrict__ flags)
 {
     __shared__ double wmax[4];
     int i = blockIdx.x * 256 + threadIdx.x;
     double d = 0;
+    bool bad = false;
     if (i < n) {
         double d0 = x[3 * i] - x0[3 * i], d1 = x[3 * i + 1] - x0[3 * i + 1], d2 = x[3 * i + 2] - x0[3 * i + 2];
         d = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        if (d != d) d = __builtin_huge_val();   // a NaN position turns the early end off
+        bad = !isfinite(d);
+        if (bad) d = __builtin_huge_val();   // also turns the early end off
     }
+    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&flags[kFlagBadCoord], 1);
     for (int off = 32; off > 0; off >>= 1) d = fmax(d, __shfl_xor(d, off));
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = d;
     __syncthreads();
     if (threadIdx.x == 0) {
         double m = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
         if (m > 0) atomicMax(disp, (unsigned long long)__double_as_longlong(m));
+        if (m > 0 && 2.0 * m >= lim) atomicOr(&flags[kFlagSkin], 1);
     }
 }
 
 }  // namespace
 
-void launch_displacement(const dp_nlist *nl, int n, const double *x, hipStream_t st)
+void launch_displacement(const dp_nlist *nl, int n, const double *x, double lim, hipStream_t st)
 {
     if (!nl->x0 || n <= 0) return;
     launch_fill_zero_int(reinterpret_cast<int *>(nl->disp), 2, st);
-    hipLaunchKernelGGL(k_displacement, dim3(div_up(n, 256)), dim3(256), 0, st, n, x, nl->x0, nl->disp);
+    hipLaunchKernelGGL(k_displacement, dim3(div_up(n, 256)), dim3(256), 0, st, n, x, nl->x0, lim, nl->disp,
+                       nl->flags);
 }
 
 void launch_fill_zero_int(int *p, long n, hipStream_t st)
@@ -397,7 +410,8 @@ __global__ void k_expand_boxes(const int *__restrict__ off, const double *__rest
 __global__ void __launch_bounds__(256) k_segment_reduce(const int *__restrict__ off,
                                                         const double *__restrict__ e_atom,
                                                         const double *__restrict__ w_atom,
-                                                        double *__restrict__ energy, double *__restrict__ virial)
+                                                        double *__restrict__ energy, double *__restrict__ virial,
+                                                        int *__restrict__ flags)
 {
     __shared__ double sh[256][10];
     int r = blockIdx.x, t = threadIdx.x;
@@ -416,14 +430,16 @@ __global__ void __launch_bounds__(256) k_segment_reduce(const int *__restrict__ 
     }
     if (t == 0 && energy) energy[r] = sh[0][0];
     if (t < 9 && virial && w_atom) virial[9 * r + t] = sh[0][1 + t];
+    if (t < 10 && !isfinite(sh[0][t])) atomicOr(&flags[kFlagNonFinite], 1);
 }
 
 }  // namespace
 
 void launch_segment_reduce(int nreq, const int *offsets, const double *e_atom, const double *w_atom,
-                           double *energy, double *virial, hipStream_t st)
+                           double *energy, double *virial, int *flags, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_segment_reduce, dim3(nreq), dim3(256), 0, st, offsets, e_atom, w_atom, energy, virial);
+    hipLaunchKernelGGL(k_segment_reduce, dim3(nreq), dim3(256), 0, st, offsets, e_atom, w_atom, energy, virial,
+                       flags);
 }
 
 void launch_expand_boxes(int nreq, const int *offsets, const double *Lreq, double *atomL, hipStream_t st)

@@ -130,7 +130,7 @@ namespace {
 // tanh on [0, 8) by a quadratic per interval of width 1/128: the value and
 // slope of tanh at the left node x0 and its value at x0 + h (paper Sec. 3.5
 // fixes the order, the range, the odd extension and the saturation at 8).
-__global__ void k_tanh_table(float *tab)
+__global__ void k_tanh_table(double *tab64, float *tab32)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= kTanhN) return;
@@ -138,17 +138,18 @@ __global__ void k_tanh_table(float *tab)
     double x0 = k * h;
     double a0 = tanh(x0), a1 = 1.0 - a0 * a0;
     double a2 = (tanh(x0 + h) - a0 - a1 * h) / (h * h);
-    tab[4 * k] = (float)a0;
-    tab[4 * k + 1] = (float)a1;
-    tab[4 * k + 2] = (float)a2;
-    tab[4 * k + 3] = 0.f;
+    double a[4] = {a0, a1, a2, 0.0};
+    for (int q = 0; q < 4; q++) {
+        tab64[4 * k + q] = a[q];
+        tab32[4 * k + q] = (float)a[q];
+    }
 }
 
 }  // namespace
 
-void launch_tanh_table(float *tab, hipStream_t st)
+void launch_tanh_table(double *tab64, float *tab32, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_tanh_table, dim3(div_up(kTanhN, 256)), dim3(256), 0, st, tab);
+    hipLaunchKernelGGL(k_tanh_table, dim3(div_up(kTanhN, 256)), dim3(256), 0, st, tab64, tab32);
 }
 
 }  // namespace dp

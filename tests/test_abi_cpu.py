@@ -61,6 +61,19 @@ def test_bad_arguments_are_rejected():
     assert _lib.lib.dp_compute(None, None, 0, None, None, None, 0, 0, None, None, None, None, None) == -1
     assert _lib.lib.dp_model_destroy(None) == 0
     assert _lib.lib.dp_nlist_destroy(None) == 0
+    assert _lib.lib.dp_nlist_check(None) == -1
+    assert _lib.lib.dp_tanh_table_download(None, None, None) == -1
+    assert _lib.lib.dp_nve_run(None, None, 0, None, None, None, None, None, 1.0, 1, 1, 2.0, 0, 0, None,
+                               None) == -1
+
+
+def test_status_codes_named():
+    """Every status the header declares has its name in the binding."""
+    from paper_2201_01446_amd import _lib
+    text = open(os.path.join(ROOT, "include", "dp.h")).read()
+    codes = {int(v): k for k, v in re.findall(r"\b(DP_[A-Z_]+)\s*=\s*(-?\d+)", text) if k.startswith(("DP_OK", "DP_ERR"))}
+    assert codes == {k: v for k, v in _lib.STATUS.items()}
+    assert codes[-8] == "DP_ERR_SKIN" and codes[-7] == "DP_ERR_NONFINITE"
 
 
 def test_bench_refuses_more_than_one_gpu():

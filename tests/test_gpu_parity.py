@@ -190,6 +190,66 @@ def test_sel_overflow_keeps_nearest(P, cu_params, sel):
         assert st["max_nei"] == int(np.max(ref["nnei"]))
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sel_cut_inside_self_image_tie(P, precision):
+    """32-atom cell (edge 7.268 A, below rcut): every atom has 134 neighbors
+    closer than the edge and its six own images exactly at it.  sel = 137
+    cuts inside that six-fold tie, so which three images are kept decides
+    E_i; both sides keep the first three in the order (r, j, image shift x,
+    y, z), i.e. the images (-1,0,0), (0,-1,0), (0,0,-1)."""
+    x, box = synth.copper(2, 0.05, 13)
+    L = box[0, 0]
+    cfg = synth.copper_model_config(sel=137)
+    p = synth.model_params(cfg)
+    for i in range(len(x)):
+        _, img, r, _ = oracle.neighbors(cfg, x, box, i)
+        assert int(np.sum(r < L)) == 134 and int(np.sum(r == L)) == 6
+        np.testing.assert_array_equal(img[134:137], [[-1, 0, 0], [0, -1, 0], [0, 0, -1]])
+    m = P.Model(cfg, p).tabulate(S_MAX, H, TAIL, H_TAIL)
+    tab = oracle.Table(cfg, p, S_MAX, H, TAIL, H_TAIL)
+    ref = oracle.evaluate(cfg, p, x, box, table=tab)
+    assert ref["dropped"] == 3 * len(x) + int(np.sum(ref["nnei"] - 140))
+    print(f"self-image tie: n={len(x)} precision={precision}", flush=True)
+    got, nl = run(P, m, x, box, precision)
+    check_against(ref, got, precision, len(x))
+    assert nl.stats()["sel_overflow"] == len(x)
+
+
+def table_overrun_cases():
+    """(name, coordinates, box, table parameters): an open cluster with one
+    pair at 0.6 A (s = 1.67, past the default table end 1.5), and a 108-atom
+    periodic cell (sigma 0.1) with a table ending at s = 0.4 (r = 2.5 A),
+    inside the spread of the nearest-neighbor shell."""
+    xc = np.array([[0.0, 0.0, 0.0], [0.6, 0.05, -0.02], [2.3, 0.4, 0.1], [-1.1, 2.2, 0.3], [0.4, -0.3, 2.5]])
+    x3, box3 = synth.copper(3, 0.1, 17)
+    return [("open_close_pair", xc, None, (S_MAX, H, TAIL, H_TAIL)),
+            ("periodic_short_table", x3, box3, (0.3, 0.01, 0.4, 0.05))]
+
+
+@pytest.mark.parametrize("case", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_table_overrun_clamp(P, cu_cfg, cu_params, case, precision):
+    """s past the table end: s is clamped to the end (G constant, G' = 0)
+    and each look-up counted.  E_i, F, W against the oracle's tabulated mode,
+    and the overrun count against the oracle's."""
+    name, x, box, targs = table_overrun_cases()[case]
+    m = P.Model(cu_cfg, cu_params).tabulate(*targs)
+    tab = oracle.Table(cu_cfg, cu_params, *targs)
+    ref = oracle.evaluate(cu_cfg, cu_params, x, box, table=tab)
+    assert ref["table_oob"] > 0
+    print(f"table overrun: case={name} n={len(x)} precision={precision} oracle oob={ref['table_oob']}", flush=True)
+    nl = P.NeighborList(m, dev(x), box, skin=2.0)
+    out = P.compute(m, nl, dev(x), precision=precision, atom_energy=True)
+    torch.cuda.synchronize()
+    got = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+    check_against(ref, got, precision, len(x))
+    oob = nl.stats()["table_oob"]
+    if precision == 0:
+        assert oob == ref["table_oob"]
+    else:   # FP32 s can round across the table end for a pair within ~1e-7 of it
+        assert abs(oob - ref["table_oob"]) <= 2
+
+
 def test_forces_are_minus_gradient_of_gpu_energy(P, model):
     """Central differences of the GPU's own FP64 energy (h = 1e-4 A)."""
     x, box = synth.copper(2, 0.1, 33)
