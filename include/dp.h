@@ -194,6 +194,28 @@ dp_status dp_compute(dp_model *model, dp_nlist *nlist, int natoms, const double 
                      double *energy_d, double *force_d, double *virial_d,
                      double *atom_energy_d, void *stream);
 
+/* dp_compute for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, hosts that forbid allocation.  Same
+ * arguments, same results (bit for bit) as dp_compute in the fused modes 0, 3
+ * and 4; the plain modes 1 and 2 return DP_ERR_UNSUPPORTED.  The list must
+ * have been built beforehand (dp_build_nlist allocates; this call does not).
+ * Its scratch (embedding outputs, descriptor, fitting-net activations and
+ * gradients, neighbor records) is not the list's but one static device
+ * array of 96 MiB per GPU, held from the library's first use on that GPU
+ * until the process ends; the call makes no hipMalloc, hipFree or other
+ * allocating call (kernel timers stay off during it).  The scratch must
+ * hold the evaluation: any natoms <= 512 of any supported model in any
+ * precision fits, one-type models at sel = 192 up to 1,408 atoms; a larger
+ * evaluation returns DP_ERR_CAPACITY before anything is enqueued.  Every
+ * call on one GPU shares that GPU's array: two calls whose work overlaps
+ * on the device (different streams, or different host threads) race and
+ * give wrong results; calls in one stream are ordered and safe.  The
+ * array needs no clearing: results depend only on what the call itself wrote. */
+dp_status dp_compute_noalloc(dp_model *model, dp_nlist *nlist, int natoms, const double *coords_d,
+                             const int *types_d, const double *box_h, int mode, int precision,
+                             double *energy_d, double *force_d, double *virial_d,
+                             double *atom_energy_d, void *stream);
+
 /* The two halves of dp_compute, for an autograd function.  dp_energy_forward
  * computes E (and E_i) and keeps the forward's activations (T, D, fitting-net
  * layers) in the list's scratch.  dp_energy_backward then runs only the

@@ -48,6 +48,7 @@ _SIG = {
     "dp_build_nlist": [_vp, _i, _vp, _vp, _vp, _d, _pvp, _vp],
     "dp_nlist_destroy": [_vp],
     "dp_compute": [_vp, _vp, _i, _vp, _vp, _vp, _i, _i, _vp, _vp, _vp, _vp, _vp],
+    "dp_compute_noalloc": [_vp, _vp, _i, _vp, _vp, _vp, _i, _i, _vp, _vp, _vp, _vp, _vp],
     "dp_descriptor": [_vp, _vp, _i, _vp, _vp, _i, _i, _vp, _vp, _vp, _vp, _vp],
     "dp_energy_forward": [_vp, _vp, _i, _vp, _i, _i, _vp, _vp, _vp],
     "dp_energy_backward": [_vp, _vp, _i, _vp, _i, _i, _vp, _vp, _vp],

@@ -131,8 +131,10 @@ class NeighborList:
 
 
 def compute(model, nlist, coords, mode=COMPRESSED, precision=FP64, forces=True, virial=True,
-            atom_energy=False, out=None):
-    """Energy (1), forces (N,3), virial (3,3), per-atom energies (N) as float64 tensors."""
+            atom_energy=False, out=None, noalloc=False):
+    """Energy (1), forces (N,3), virial (3,3), per-atom energies (N) as float64 tensors.
+    noalloc: run dp_compute_noalloc (the library's static scratch instead of
+    the list's; pass `out` tensors to keep torch from allocating as well)."""
     n = coords.shape[0]
     _f64(coords, (n, 3))
     dev = coords.device
@@ -145,8 +147,9 @@ def compute(model, nlist, coords, mode=COMPRESSED, precision=FP64, forces=True, 
     Ea = (o.get("e_atom") if o.get("e_atom") is not None else torch.empty(n, dtype=torch.float64, device=dev)) \
         if atom_energy else None
     _, bp = _box(nlist.box.reshape(3, 3) if nlist.box is not None else None)
-    check(lib.dp_compute(model.h, nlist.h, n, _ptr(coords), None, bp, mode, precision, _ptr(E), _ptr(F), _ptr(W),
-                         _ptr(Ea), _stream()))
+    fn = lib.dp_compute_noalloc if noalloc else lib.dp_compute
+    check(fn(model.h, nlist.h, n, _ptr(coords), None, bp, mode, precision, _ptr(E), _ptr(F), _ptr(W), _ptr(Ea),
+             _stream()))
     res = dict(E=E, F=F, W=W, e_atom=Ea)
     if out is not None:
         out.update({k: v for k, v in res.items() if v is not None})

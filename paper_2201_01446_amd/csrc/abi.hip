@@ -588,13 +588,20 @@ dp_status dp_nlist_destroy(dp_nlist *nl)
 
 static dp_status compute_common(dp_model *m, dp_nlist *nl, int natoms, const double *x, int mode, int precision,
                                 double *energy, double *force, double *virial, double *atom_energy, int *nnei,
-                                int *nseg, double *T, double *D, hipStream_t st, int phase = 0)
+                                int *nseg, double *T, double *D, hipStream_t st, int phase = 0,
+                                bool noalloc = false)
 {
     dp_status s = check_compute_args(m, nl, natoms, x, mode, precision);
     if (s != DP_OK) return s;
     if (phase == 2 && nl->fwd_token != precision + 1 + 8 * mode)
         return fail(DP_ERR_STATE, "no kept forward of this precision and mode on this list");
-    if ((s = ensure_ws(nl, precision, m->cfg.sel)) != DP_OK) return s;
+    if (noalloc) {
+        // the plain rungs keep their activations in a scratch of their own
+        if (mode == DP_PLAIN || mode == DP_TAB_UNFUSED)
+            return fail(DP_ERR_UNSUPPORTED, "dp_compute_noalloc runs the fused modes (0, 3, 4) only");
+    } else if ((s = ensure_ws(nl, precision, m->cfg.sel)) != DP_OK) {
+        return s;
+    }
     ComputeArgs a;
     a.m = m;
     a.nl = nl;
@@ -611,17 +618,16 @@ static dp_status compute_common(dp_model *m, dp_nlist *nl, int natoms, const dou
     a.need_forces = force || virial;
     a.force = force ? force : nl->force_tmp;
     a.phase = phase;
+    a.noalloc = noalloc;
     // any forward overwrites the kept activations
     nl->fwd_token = phase == 1 ? precision + 1 + 8 * mode : (phase == 2 ? nl->fwd_token : 0);
     a.mode = mode;
     return (mode == DP_PLAIN || mode == DP_TAB_UNFUSED) ? run_plain(a, st) : run_compressed(a, st);
 }
 
-dp_status dp_compute(dp_model *m, dp_nlist *nl, int natoms, const double *coords_d, const int *types_d,
-                     const double *box_h, int mode, int precision, double *energy_d, double *force_d,
-                     double *virial_d, double *atom_energy_d, void *stream)
+// The box check shared by dp_compute and dp_compute_noalloc.
+static dp_status check_box(const dp_nlist *nl, const double *box_h)
 {
-    (void)types_d;
     if (nl && nl->periodic) {
         double L[3];
         if (!box_h || !box_ok(box_h, L) || L[0] != nl->L[0] || L[1] != nl->L[1] || L[2] != nl->L[2])
@@ -629,8 +635,32 @@ dp_status dp_compute(dp_model *m, dp_nlist *nl, int natoms, const double *coords
     } else if (nl && box_h) {
         return fail(DP_ERR_ARG, "the list was built for an open cluster");
     }
+    return DP_OK;
+}
+
+dp_status dp_compute(dp_model *m, dp_nlist *nl, int natoms, const double *coords_d, const int *types_d,
+                     const double *box_h, int mode, int precision, double *energy_d, double *force_d,
+                     double *virial_d, double *atom_energy_d, void *stream)
+{
+    (void)types_d;
+    dp_status s = check_box(nl, box_h);
+    if (s != DP_OK) return s;
     return compute_common(m, nl, natoms, coords_d, mode, precision, energy_d, force_d, virial_d, atom_energy_d,
                           nullptr, nullptr, nullptr, nullptr, (hipStream_t)stream);
+}
+
+dp_status dp_compute_noalloc(dp_model *m, dp_nlist *nl, int natoms, const double *coords_d, const int *types_d,
+                             const double *box_h, int mode, int precision, double *energy_d, double *force_d,
+                             double *virial_d, double *atom_energy_d, void *stream)
+{
+    (void)types_d;
+    dp_status s = check_box(nl, box_h);
+    if (s != DP_OK) return s;
+    timers_quiet(true);
+    s = compute_common(m, nl, natoms, coords_d, mode, precision, energy_d, force_d, virial_d, atom_energy_d,
+                       nullptr, nullptr, nullptr, nullptr, (hipStream_t)stream, 0, true);
+    timers_quiet(false);
+    return s;
 }
 
 dp_status dp_energy_forward(dp_model *m, dp_nlist *nl, int natoms, const double *coords_d, int mode,

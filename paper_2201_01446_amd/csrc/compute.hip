@@ -15,6 +15,7 @@
 
 #include "dp_internal.h"
 
+#include <mutex>
 #include <type_traits>
 
 namespace dp {
@@ -230,10 +231,64 @@ dp_status ensure_ws(dp_nlist *nl, int precision, int sel)
     return DP_OK;
 }
 
+// Scratch of dp_compute_noalloc, for callers that cannot allocate device
+// memory: one fixed array per device, shared by every such call on that
+// device (calls that overlap on one device race).  Nothing in it needs
+// clearing between calls: every element a call reads was written earlier in
+// the same call, except the pad rows of the GEMM operands (rows past the
+// last atom), whose outputs are never read and which cannot mix with other
+// rows.  96 MiB holds the workspace of 512 atoms of any supported model
+// (sel <= 512, up to 4 types) in any precision, or of up to 1,408 one-type
+// atoms at sel = 192.
+namespace {
+constexpr size_t kNoAllocBytes = (size_t)96 << 20;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, looked up once per
+// device (the host-side name of the array is not a device address).
+dp_status scratch_on_device(void **out)
+{
+    int dev = 0;
+    DP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(DP_ERR_UNSUPPORTED, "device ordinal beyond 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(DP_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return DP_OK;
+}
+}  // namespace
+
+size_t noalloc_scratch_bytes() { return kNoAllocBytes; }
+
 dp_status run_compressed(const ComputeArgs &a, hipStream_t st)
 {
-    int np = (int)fit_rows(a.nl->alloc_atoms, a.nl->ntypes);
-    WS w = carve(a.nl->ws, np, a.precision, a.m->cfg.sel);
+    int np;
+    void *base;
+    if (a.noalloc) {
+        // carved for exactly the rows of this call
+        np = (int)fit_rows(a.natoms, a.nl->ntypes);
+        size_t need = ws_bytes_for(np, a.precision, a.m->cfg.sel);
+        if (need > kNoAllocBytes)
+            return fail(DP_ERR_CAPACITY, "the evaluation needs " + std::to_string(need) +
+                                             " bytes of scratch, more than the static " +
+                                             std::to_string(kNoAllocBytes) + " of dp_compute_noalloc");
+        dp_status s = scratch_on_device(&base);
+        if (s != DP_OK) return s;
+    } else {
+        np = (int)fit_rows(a.nl->alloc_atoms, a.nl->ntypes);
+        base = a.nl->ws;
+    }
+    WS w = carve(base, np, a.precision, a.m->cfg.sel);
     if (a.precision == DP_FP64) return run_t<double, double, false>(a, w, np, a.m->w64, a.m->fitb_d, st);
     if (a.precision == DP_FP32) return run_t<float, float, false>(a, w, np, a.m->w32, a.m->fitb_f, st);
     return run_t<__bf16, float, false>(a, w, np, a.m->wbf, a.m->fitb_f, st);

@@ -190,8 +190,8 @@ class TimerScope {
 // asynchronous kernel failure to the named step.
 dp_status step_check(const char *name, hipStream_t st);
 
-inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
-inline long round_up(long a, long b) { return (a + b - 1) / b * b; }
+constexpr int div_up(long a, long b) { return (int)((a + b - 1) / b); }
+constexpr long round_up(long a, long b) { return (a + b - 1) / b * b; }
 
 // XCD-aware work order.  The dispatcher deals the blocks of a grid round-robin
 // over the 8 XCDs (each with its own L2), so block b runs on XCD b % 8.  A
@@ -329,6 +329,7 @@ struct ComputeArgs {
     int mode = 0;                  // dp_mode
     int nseg = 0;                  // >0: E and W per segment (request) of a batch instead of totals
     const int *seg_off = nullptr;  // device [nseg + 1] atom offsets of the segments
+    bool noalloc = false;          // scratch from the library's static device array, not the list's
 };
 // tabulated: the tabulated-but-unfused rung (G materialised from the table)
 template <typename real, typename TD>
@@ -352,6 +353,11 @@ void launch_reverse(dp_nlist *nl, int off, int n, hipStream_t st);
 void launch_force_gather(const dp_model *m, const dp_nlist *nl, int n, const double *x, int precision,
                          const void *rec, const int *rcnt, double *force, hipStream_t st);
 size_t ws_bytes_for_atoms(int natoms, int precision, int sel, int ntypes);
+// The static scratch of dp_compute_noalloc: its size in bytes (fixed at
+// build time) and the calling thread's switch that keeps the kernel timers
+// from creating events during such a call.
+size_t noalloc_scratch_bytes();
+void timers_quiet(bool on);
 dp_status run_compressed(const ComputeArgs &a, hipStream_t st);
 dp_status run_plain(const ComputeArgs &a, hipStream_t st);
 // Per-type kick factors 0.5 dt / m (A/fs per eV/A) and kinetic-energy

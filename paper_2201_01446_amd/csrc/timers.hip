@@ -20,6 +20,7 @@ std::mutex g_mu;
 bool g_on = false;
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
+thread_local bool t_quiet = false;   // no events from this thread (dp_compute_noalloc)
 
 hipEvent_t get_event()
 {
@@ -36,6 +37,7 @@ hipEvent_t get_event()
 
 TimerScope::TimerScope(const char *name, hipStream_t st) : name_(name), st_(st)
 {
+    if (t_quiet) return;
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_on) return;
     a_ = get_event();
@@ -45,11 +47,13 @@ TimerScope::TimerScope(const char *name, hipStream_t st) : name_(name), st_(st)
 
 TimerScope::~TimerScope()
 {
-    std::lock_guard<std::mutex> lk(g_mu);
     if (!a_ || !b_) return;
+    std::lock_guard<std::mutex> lk(g_mu);
     (void)hipEventRecord(b_, st_);
     g_recs.push_back(Rec{name_, a_, b_});
 }
+
+void timers_quiet(bool on) { t_quiet = on; }
 
 }  // namespace dp
 
