@@ -8,10 +8,14 @@ One step = half kick + drift (+ rebuild) + energy/forces/virial + half kick.
 
     python bench.py [--gpus 1] [--steps 100] [--warmup 10]
 
-Prints one JSON line: atom-steps/s of the FP32 compressed path (value), the
-FP64 compressed path beside it, per-kernel times from HIP events recorded on
-the launch stream, the roofline of the dominant kernel, and the FP64 CPU
-oracle timed on a bounded sample of the same workload on the host cores.
+Prints one JSON line: atom-steps/s of the FP64 compressed path (value: the
+paper's arithmetic), the FP32 and mixed-precision paths and the plain
+(untabulated) path beside it, per-kernel times from HIP events recorded on
+the launch stream, the roofline of each path's dominant kernel, the
+1,048,576-atom mixed-precision run and the 500,000-atom autograd step, and
+the FP64 CPU oracle on the host cores: its rate (the CPU baseline) and its
+values at sampled atoms of every timed run's final configuration (the
+accuracy gate: force RMSE and energy error per atom).
 """
 import argparse
 import json
@@ -64,9 +68,16 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--ncell", type=int, default=30)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg (baseline and accuracy gate)")
+    ap.add_argument("--no-reduced", action="store_true", help="FP64 only (no FP32 and mixed legs)")
+    ap.add_argument("--cpu-samples", type=int, default=512,
+                    help="oracle energies sampled per FP64 run (forces: one eighth; other runs half of each)")
+    ap.add_argument("--no-big", action="store_true", help="skip the 1,048,576-atom mixed-precision run")
+    ap.add_argument("--big-ncell", type=int, default=64)
+    ap.add_argument("--big-steps", type=int, default=50)
+    ap.add_argument("--no-autograd", action="store_true", help="skip the 500,000-atom autograd timing")
+    ap.add_argument("--grad-ncell", type=int, default=50)
+    ap.add_argument("--grad-iters", type=int, default=10)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--serve-requests", type=int, default=4096)
@@ -122,12 +133,71 @@ def run_nve(P, model, x0, v0, box, steps, warmup, precision, mode=0, keep=False,
     return out
 
 
+def kernel_work(N, sum_nei, sum_seg, rs):
+    """Algorithmic work per launch of each kernel (FMA = 2 FLOP) and its
+    bound: the fitting GEMMs count the model's 240 columns (not the padded
+    256) and one pass of K (not the BF16 hi/lo split's three); the embedding
+    kernels count the interval-moment form they execute: forward 24 moments
+    per neighbor, 24 per (segment, column), D 16 x 128 x 4; backward dE/dT
+    2 x 16 x 128 x 4, 24 per (segment, column), 40 per neighbor."""
+    fit_in = N * 2.0 * 240 * 2048          # 2048 -> 240 (and its transpose)
+    fit_hid = N * 2.0 * 240 * 240          # 240 -> 240
+    return {
+        "emb_fwd": (2.0 * (24 * sum_nei + 24 * 128 * sum_seg + 8192 * N), "alu"),
+        "emb_bwd": (2.0 * (16384 * N + 24 * 128 * sum_seg + 40 * sum_nei), "alu"),
+        "fit_fwd1": (fit_in, "mfma"), "fit_bwd1": (fit_in, "mfma"),
+        "fit_fwd2": (fit_hid, "mfma"), "fit_fwd3": (fit_hid, "mfma"),
+        "fit_bwd3": (fit_hid, "mfma"), "fit_bwd2": (fit_hid, "mfma"),
+        "dT": (N * 3072.0 * rs, "hbm"),      # read dD (2048) and T (512), write dT (512)
+    }
+
+
+def roofline(res, steps, work, dt_alu, dt_mfma, counter_tag):
+    """Per-kernel average launch time (HIP events on the launch stream),
+    work, bound and fraction of the published peak; the dominant kernel (the
+    largest time per step) is the roofline of the line.  VALU-bound rows also
+    give the fraction of the unpacked FP32 rate (78.6 TFLOP/s), the most this
+    build can issue (it compiles without packed FP32)."""
+    table = {}
+    for name, (tot_ms, cnt) in res["kernels"].items():
+        avg = tot_ms / max(cnt, 1)
+        row = dict(avg_ms=round(avg, 4), launches_per_step=round(cnt / steps, 3))
+        if name in work:
+            w, bound = work[name]
+            if bound == "hbm":
+                ach, peak, unit = w / (avg * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s"
+            else:
+                dt = dt_alu if bound == "alu" else dt_mfma
+                ach, peak, unit = w / (avg * 1e-3) / 1e12, PEAK[(bound, dt)], "TFLOP/s"
+            row.update(bound=bound, achieved=round(ach, 3), peak=peak, unit=unit, frac=round(ach / peak, 4))
+            if bound == "alu" and dt_alu == "f32":
+                row["frac_of_unpacked_78.6"] = round(ach / 78.6, 4)
+        table[name] = row
+    dom = max((n for n in table if "frac" in table[n]),
+              key=lambda n: table[n]["avg_ms"] * table[n]["launches_per_step"])
+    t = table[dom]
+    roof = dict(bound=t["bound"], achieved=t["achieved"], peak=t["peak"], unit=t["unit"], frac=t["frac"],
+                traffic=measured_traffic(dom, counter_tag), kernel=dom, per_launch_work=work[dom][0],
+                avg_ms=t["avg_ms"])
+    return roof, table
+
+
+def final_state(P, model, res, precision):
+    """E_i and forces of the run's final configuration (one more evaluation,
+    outside the timed region), as host arrays for the accuracy gate."""
+    import torch
+    out = P.compute(model, res["nl"], res["x"], precision=precision, atom_energy=True)
+    torch.cuda.synchronize()
+    return dict(x=res["x"].cpu().numpy(), e_atom=out["e_atom"].cpu().numpy(), F=out["F"].cpu().numpy())
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the per-GPU share is the "
               "108,000-atom kernel measured at --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    import gc
     import torch
 
     import paper_2201_01446_amd as P
@@ -150,109 +220,93 @@ def main():
     N = len(x0)
     K, W = args.steps, args.warmup
 
-    res32 = run_nve(P, model, x0, v0, box, K, W, P.FP32, keep=True)
-    res64 = None if args.no_fp64 else run_nve(P, model, x0, v0, box, K, W, P.FP64)
-    resbf = run_nve(P, model, x0, v0, box, K, W, P.MIXED_BF16)
+    # the headline: FP64, the paper's arithmetic; then FP32 and mixed beside it
+    legs = [("fp64", P.FP64, "f64", "f64", 8)]
+    if not args.no_reduced:
+        legs += [("fp32", P.FP32, "f32", "f32", 4), ("mixed_bf16", P.MIXED_BF16, "f32", "bf16", 4)]
+    runs, finals = {}, {}
+    for name, prec, _, _, _ in legs:
+        r = run_nve(P, model, x0, v0, box, K, W, prec, keep=True)
+        finals[name] = final_state(P, model, r, prec)
+        if name == "fp64":
+            # neighbor statistics of the final configuration (for the work counts)
+            d = P.descriptor(model, r["nl"], r["x"], precision=P.FP64)
+            sum_nei = int(d["nnei"].sum().item())
+            sum_seg = int(d["nseg"].sum().item())
+            del d
+        r.pop("nl")
+        r.pop("x")
+        runs[name] = r
+        gc.collect()
     # the plain (untabulated, padded, materialised) path: same MD protocol,
     # fewer steps (it is the denominator of the speed-up)
     Kp = max(1, min(K, args.plain_steps))
-    plain32 = None if args.no_plain else run_nve(P, model, x0, v0, box, Kp, 1, P.FP32, mode=P.PLAIN)
-    plain64 = None if (args.no_plain or args.no_fp64) else run_nve(P, model, x0, v0, box, Kp, 1, P.FP64,
-                                                                    mode=P.PLAIN)
+    plain = {}
+    if not args.no_plain:
+        for name, prec in (("plain_fp64", P.FP64), ("plain_fp32", P.FP32)):
+            if name == "plain_fp32" and args.no_reduced:
+                continue
+            plain[name] = run_nve(P, model, x0, v0, box, Kp, 1, prec, mode=P.PLAIN)
+            gc.collect()
 
-    # neighbor statistics of the final configuration (for the FLOP counts)
-    d = P.descriptor(model, res32["nl"], res32["x"], precision=P.FP32)
-    sum_nei = int(d["nnei"].sum().item())
-    sum_seg = int(d["nseg"].sum().item())
+    summary = {}
+    for name, prec, dt_alu, dt_mfma, rs in legs:
+        r = runs[name]
+        roof, per = roofline(r, K, kernel_work(N, sum_nei, sum_seg, rs), dt_alu, dt_mfma,
+                             {"fp64": "f64", "fp32": "f32", "mixed_bf16": "bf16"}[name])
+        th = r["thermo"]
+        etot = th[:, 0] + th[:, 1]
+        v = N * K / (r["ms"] * 1e-3)
+        summary[name] = {"value": round(v, 1), "ms_per_step": round(r["ms"] / K, 4),
+                         "ns_per_day": round(v / N * 86400 * 1e-6, 3), "roofline": roof, "kernels": per,
+                         "energy_drift_eV_per_atom": float((etot[-1] - etot[0]) / N)}
+    for name, r in plain.items():
+        vp = N * Kp / (r["ms"] * 1e-3)
+        comp = summary.get(name.replace("plain_", ""), {}).get("value")
+        summary[name] = {"value": round(vp, 1), "ms_per_step": round(r["ms"] / Kp, 4), "steps": Kp,
+                         "kernels": {k: round(t[0] / max(t[1], 1), 4) for k, t in r["kernels"].items()},
+                         "speedup_compressed_vs_plain": round(comp / vp, 3) if comp else None}
+        tr = plain_traffic(r["kernels"], "f64" if name.endswith("64") else "f32", Kp)
+        if tr:
+            summary[name]["roofline"] = tr
+    del runs, plain
+    gc.collect()
 
-    def roofline(res, dt, rs):
-        """Per-kernel algorithmic work per launch and the dominant kernel's
-        roofline (the kernel with the largest time per step)."""
-        kern = res["kernels"]
-        fit_in = N * 2.0 * 240 * 2048          # 2048 -> 240 (and its transpose)
-        fit_hid = N * 2.0 * 240 * 240          # 240 -> 240
-        # embedding kernels in the interval-moment form they execute (FMA = 2 FLOP):
-        # forward 24 moments per neighbor, 24 per (segment, column), D 16 x 128 x 4;
-        # backward dE/dT 2 x 16 x 128 x 4, 24 per (segment, column), 40 per neighbor
-        work = {   # name: (work per launch, bound)
-            "emb_fwd": (2.0 * (24 * sum_nei + 24 * 128 * sum_seg + 8192 * N), "alu"),
-            "emb_bwd": (2.0 * (16384 * N + 24 * 128 * sum_seg + 40 * sum_nei), "alu"),
-            "fit_fwd1": (fit_in, "mfma"), "fit_bwd1": (fit_in, "mfma"),
-            "fit_fwd2": (fit_hid, "mfma"), "fit_fwd3": (fit_hid, "mfma"),
-            "fit_bwd3": (fit_hid, "mfma"), "fit_bwd2": (fit_hid, "mfma"),
-            "dT": (N * 3072.0 * rs, "hbm"),      # read dD (2048) and T (512), write dT (512)
-        }
-        table = {}
-        for name, (tot_ms, cnt) in kern.items():
-            avg = tot_ms / max(cnt, 1)
-            row = dict(avg_ms=round(avg, 4), launches_per_step=round(cnt / K, 3))
-            if name in work:
-                w, bound = work[name]
-                if bound == "hbm":
-                    ach, peak, unit = w / (avg * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s"
-                else:
-                    ach, peak, unit = w / (avg * 1e-3) / 1e12, PEAK[(bound, dt)], "TFLOP/s"
-                row.update(bound=bound, achieved=round(ach, 3), peak=peak, unit=unit, frac=round(ach / peak, 4))
-            table[name] = row
-        dom = max((n for n in table if "frac" in table[n]),
-                  key=lambda n: table[n]["avg_ms"] * table[n]["launches_per_step"])
-        t = table[dom]
-        roof = dict(bound=t["bound"], achieved=t["achieved"], peak=t["peak"], unit=t["unit"], frac=t["frac"],
-                    traffic=measured_traffic(dom, dt), kernel=dom, per_launch_work=work[dom][0],
-                    avg_ms=t["avg_ms"])
-        return dom, roof, table
+    big = None if args.no_big else config_1m(P, model, args.big_ncell, args.big_steps)
+    grad = None if args.no_autograd else config_autograd(P, model, args.grad_ncell, args.grad_iters)
+    gc.collect()
 
-    dom, roof, per32 = roofline(res32, "f32", 4)
-    value = N * K / (res32["ms"] * 1e-3)
-    ms_step = res32["ms"] / K
-
-    # FP32 energy conservation over the run
-    th = res32["thermo"]
-    etot = th[:, 0] + th[:, 1]
-
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(cfg, params, x0, box, args.cpu_seconds)
-
+    head = summary["fp64"]
     out = {
-        "metric": "atom-steps/s on 1 GPU, compressed DP MD step (FP32), force RMSE <= 1e-3 eV/A",
-        "value": round(value, 1),
+        "metric": "atom-steps/s on 1 GPU, compressed DP MD step (FP64), force RMSE <= 1e-3 eV/A",
+        "value": head["value"],
         "unit": "atom-steps/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64",
         "data": "synthetic: seeded FCC Cu + Gaussian displacements, seeded random weights",
-        "config": {"workload": f"Cu FCC {args.ncell}^3 cells ({N} atoms), sigma 0.05 A, NVE dt 1 fs, "
+        "config": {"workload": f"Cu FCC {args.ncell}^3 cells ({N} atoms), sigma 0.05 A, 330 K, NVE dt 1 fs, "
                                "nlist skin 2 A rebuilt every 10 steps, compressed (stride 0.01, tail 0.1)",
-                   "natoms": N, "precision": "fp32", "mode": "compressed"},
-        "ns_per_day": round(value / N * 86400 * 1e-6, 3),
-        "roofline": roof,
-        "kernels_fp32": per32,
-        "energy_drift_fp32_eV_per_atom": float((etot[-1] - etot[0]) / N),
+                   "natoms": N, "precision": "fp64", "mode": "compressed"},
+        "ns_per_day": head["ns_per_day"],
+        "roofline": head["roofline"],
+        "kernels_fp64": head["kernels"],
+        "energy_drift_fp64_eV_per_atom": head["energy_drift_eV_per_atom"],
         "mean_neighbors": sum_nei / N,
         "mean_interval_segments": sum_seg / N,
     }
-    if res64 is not None:
-        v64 = N * K / (res64["ms"] * 1e-3)
-        _, roof64, per64 = roofline(res64, "f64", 8)
-        out["fp64"] = {"value": round(v64, 1), "ms_per_step": round(res64["ms"] / K, 4),
-                       "roofline": roof64, "kernels": per64}
-    vbf = N * K / (resbf["ms"] * 1e-3)
-    out["mixed_bf16"] = {"value": round(vbf, 1), "ms_per_step": round(resbf["ms"] / K, 4),
-                         "kernels": {k: round(v[0] / max(v[1], 1), 4) for k, v in resbf["kernels"].items()}}
-    for name, res, comp in (("plain_fp32", plain32, value), ("plain_fp64", plain64,
-                                                             out.get("fp64", {}).get("value"))):
-        if res is None:
-            continue
-        vp = N * Kp / (res["ms"] * 1e-3)
-        out[name] = {"value": round(vp, 1), "ms_per_step": round(res["ms"] / Kp, 4), "steps": Kp,
-                     "kernels": {k: round(v[0] / max(v[1], 1), 4) for k, v in res["kernels"].items()},
-                     "speedup_compressed_vs_plain": round(comp / vp, 3) if comp else None}
+    for name in ("fp32", "mixed_bf16", "plain_fp64", "plain_fp32"):
+        if name in summary:
+            out[name] = summary[name]
+    if big is not None:
+        out["config_1m_mixed"] = {k: v for k, v in big.items() if k not in ("final", "box")}
+    if grad is not None:
+        out["config_autograd_500k"] = {k: v for k, v in grad.items() if k not in ("final", "box")}
     if not args.no_tanh:
         out["tanh_table"] = tanh_compare(P, cfg, params, x0, v0, box, min(K, 50))
     if not args.no_ablation:
@@ -263,9 +317,155 @@ def main():
         out["serving"] = serving(P, model, args.serve_requests)
     if not args.no_water:
         out["water"] = water(P, args.water_rep, min(K, 50), W)
-    if cpu is not None:
+    if not args.no_cpu:
+        # the oracle leg: its timing is the CPU baseline, and its values at
+        # sampled atoms of each timed run's final configuration are the
+        # accuracy gate of that run
+        cases = {name: (finals[name], box) for name in finals}
+        if big is not None:
+            cases["config_1m_mixed"] = (big["final"], big["box"])
+        if grad is not None:
+            cases["config_autograd_500k"] = (grad["final"], grad["box"])
+        cpu, gate = oracle_leg(cfg, params, cases, args.cpu_samples)
         out["cpu_baseline"] = cpu
+        out["accuracy"] = gate
+        for name, g in gate.items():
+            tgt = out if name == "fp64" else out.get(name)
+            if isinstance(tgt, dict):
+                tgt["accuracy_gate_pass"] = g["pass"]
     print(json.dumps(out))
+
+
+def plain_traffic(kern, tag, steps):
+    """HBM roofline of the plain path's dominant kernel from the committed
+    counters (None when there are none for these sources)."""
+    best = max(kern.items(), key=lambda kv: kv[1][0], default=None)
+    if best is None:
+        return None
+    name, (tot, cnt) = best
+    b = measured_traffic(name, tag)
+    if b is None:
+        return None
+    avg = tot / max(cnt, 1)
+    ach = b / (avg * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(ach / HBM_PEAK_GBS, 4), traffic=b, kernel=name, avg_ms=round(avg, 4),
+                launches_per_step=round(cnt / steps, 3))
+
+
+def config_1m(P, model, ncell, steps):
+    """The large mixed-precision run: 4 ncell^3 atoms of copper (64^3 cells:
+    1,048,576 atoms), sigma 0.08 A, 330 K, 50 NVE steps in the mixed mode
+    (FP32 table and contraction, BF16 fitting GEMMs, FP64 reductions and
+    integration)."""
+    import gc
+    import synth
+    x0, box = synth.copper(ncell, 0.08, synth.SEED_CFG[3])
+    v0 = synth.maxwell_boltzmann(len(x0), 330.0, seed=synth.SEED_VELOCITY + 1)
+    N = len(x0)
+    r = run_nve(P, model, x0, v0, box, steps, 2, P.MIXED_BF16, keep=True)
+    fin = final_state(P, model, r, P.MIXED_BF16)
+    st = r["nl"].stats()
+    th = r["thermo"]
+    etot = th[:, 0] + th[:, 1]
+    v = N * steps / (r["ms"] * 1e-3)
+    out = {"workload": f"Cu FCC {ncell}^3 cells ({N} atoms), sigma 0.08 A, 330 K, NVE dt 1 fs, nlist skin 2 A "
+                       "rebuilt every 10 steps, mixed precision (BF16 fitting GEMMs)",
+           "natoms": N, "steps": steps, "value": round(v, 1), "unit": "atom-steps/s",
+           "ms_per_step": round(r["ms"] / steps, 4), "ns_per_day": round(v / N * 86400 * 1e-6, 3),
+           "energy_drift_eV_per_atom": float((etot[-1] - etot[0]) / N), "table_oob": st["table_oob"],
+           "sel_overflow": st["sel_overflow"],
+           "kernels": {k: round(t[0] / max(t[1], 1), 4) for k, t in r["kernels"].items()},
+           "final": fin, "box": box}
+    del r
+    gc.collect()
+    return out
+
+
+def config_autograd(P, model, ncell, iters):
+    """Differentiation at scale: 4 ncell^3 atoms of copper (50^3 cells:
+    500,000 atoms), sigma 0.1 A, FP32; one iteration = DPEnergy forward
+    (energy, activations kept) + backward (forces through the hand-written
+    adjoint, G recomputed), timed over `iters` iterations."""
+    import torch
+    import synth
+    from paper_2201_01446_amd.autograd import DPEnergy
+    x0, box = synth.copper(ncell, 0.1, synth.SEED_CFG[4])
+    N = len(x0)
+    x = torch.tensor(x0, dtype=torch.float64, device="cuda")
+    nl = P.NeighborList(model, x, box, skin=2.0)
+    xg = x.clone().requires_grad_(True)
+
+    def step():
+        E = DPEnergy.apply(xg, model, nl, P.FP32, P.COMPRESSED)
+        (g,) = torch.autograd.grad(E.sum(), xg)
+        return E, g
+
+    step()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(iters):
+        E, g = step()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / iters
+    e_atom = P.compute(model, nl, x, precision=P.FP32, atom_energy=True)["e_atom"]
+    fin = dict(x=x0, e_atom=e_atom.cpu().numpy(), F=-g.detach().cpu().numpy())
+    v = N / (ms * 1e-3)
+    return {"workload": f"Cu FCC {ncell}^3 cells ({N} atoms), sigma 0.1 A, FP32, DPEnergy forward + backward "
+                        "(forces by the hand-written adjoint, G recomputed)",
+            "natoms": N, "iterations": iters, "ms_per_iteration": round(ms, 4), "value": round(v, 1),
+            "unit": "atom-evaluations/s (energy + gradient)", "final": fin, "box": box}
+
+
+def oracle_leg(cfg, params, cases, nsamp):
+    """The FP64 oracle on the host cores, untabulated and as it stands.  For
+    every timed run, at random atoms of its final configuration: E_i (from
+    the atoms within rcut) and the force (from the energies of every atom
+    within rcut of it, on a cut-out of radius 2 rcut + 0.5 A: the same
+    definition on the same neighborhoods).  Returns the CPU baseline (the
+    rate of the force cut-outs: atom energies with their gradients per
+    second) and per run the gate: RMSE_F over the sampled force components,
+    |mean dE_i| (the estimate of |dE|/N), max |dE_i|."""
+    import importlib.util
+    import oracle
+    spec = importlib.util.spec_from_file_location("dp_sampling", os.path.join(ROOT, "tests", "sampling.py"))
+    smp = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(smp)
+    gate = {}
+    centers = 0
+    t_force = 0.0
+    nf_total = 0
+    for name, (fin, box) in cases.items():
+        ne, nf = (nsamp, nsamp // 8) if name == "fp64" else (nsamp // 2, nsamp // 16)
+        s = smp.LocalSampler(cfg, params, None, fin["x"], box)
+        rng = np.random.default_rng(7)
+        e_idx = rng.choice(len(fin["x"]), ne, replace=False)
+        f_idx = rng.choice(len(fin["x"]), max(1, nf), replace=False)
+        e_ref = np.array([s.energy(int(k)) for k in e_idx])
+        t = time.perf_counter()
+        F_ref = []
+        for k in f_idx:
+            idx, _, r = s._cut(int(k), s.radius)
+            centers += int(np.sum(r < cfg["rcut"]))
+            F_ref.append(s.force(int(k)))
+        t_force += time.perf_counter() - t
+        nf_total += len(f_idx)
+        F_ref = np.array(F_ref)
+        dE = fin["e_atom"][e_idx] - e_ref
+        rmse_F = float(np.sqrt(np.mean((fin["F"][f_idx] - F_ref) ** 2)))
+        F_rms = float(np.sqrt(np.mean(F_ref ** 2)))
+        gate[name] = {"sampled_energies": int(ne), "sampled_forces": int(len(f_idx)),
+                      "rmse_F": rmse_F, "rmse_F_rel": rmse_F / max(F_rms, 1e-300), "F_rms_oracle": F_rms,
+                      "dE_per_atom": float(abs(np.mean(dE))), "max_abs_dE_i": float(np.max(np.abs(dE))),
+                      "pass": bool(rmse_F <= 1e-3 and abs(np.mean(dE)) <= 1e-5)}
+    cpu = {"value": round(centers / t_force, 2), "unit": "atom-steps/s", "cores": oracle.num_threads(),
+           "kind": "oracle",
+           "sample": f"{nf_total} force cut-outs at random atoms of the final configurations of the timed runs "
+                     f"({centers} atom energies with gradients, untabulated FP64 oracle, {t_force:.1f} s)"}
+    return cpu, gate
 
 
 def water(P, nrep, steps, warmup):
@@ -429,26 +629,6 @@ def serving(P, model, nreq):
             "closed_loop": {k: round(closed[k], 4) for k in keep},
             "poisson": dict({k: round(pois[k], 4) for k in keep}, rate_req_per_s=round(rate, 2)),
             "request_generation_s": round(gen_s, 2)}
-
-
-def cpu_baseline(cfg, params, x, box, seconds):
-    """The FP64 oracle (untabulated, as it stands) timed on a bounded sample:
-    energy and force contributions of a random subset of the atoms of the
-    same configuration; rate = sampled atoms / wall time."""
-    import oracle
-    rng = np.random.default_rng(0)
-    probe = rng.choice(len(x), 64, replace=False).astype(np.int32)
-    t = time.perf_counter()
-    oracle.evaluate(cfg, params, x, box, centers=probe)
-    tp = time.perf_counter() - t
-    n = int(min(len(x), max(64, 64 * seconds / max(tp, 1e-3))))
-    sample = rng.choice(len(x), n, replace=False).astype(np.int32)
-    t = time.perf_counter()
-    oracle.evaluate(cfg, params, x, box, centers=sample)
-    dt = time.perf_counter() - t
-    return {"value": round(n / dt, 2), "unit": "atom-steps/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"E_i and force contributions of {n} random atoms of the {len(x)}-atom workload "
-                      f"(untabulated FP64 oracle, {dt:.1f} s)"}
 
 
 if __name__ == "__main__":
