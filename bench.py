@@ -148,6 +148,8 @@ def kernel_work(N, sum_nei, sum_seg, rs):
         "fit_fwd1": (fit_in, "mfma"), "fit_bwd1": (fit_in, "mfma"),
         "fit_fwd2": (fit_hid, "mfma"), "fit_fwd3": (fit_hid, "mfma"),
         "fit_bwd3": (fit_hid, "mfma"), "fit_bwd2": (fit_hid, "mfma"),
+        # the fused tail: the two 240 -> 240 layers and their two input-gradient products
+        "fit_tail": (4 * fit_hid, "mfma"),
         "dT": (N * 3072.0 * rs, "hbm"),      # read dD (2048) and T (512), write dT (512)
     }
 

@@ -217,10 +217,14 @@ dp_status dp_compute_noalloc(dp_model *model, dp_nlist *nlist, int natoms, const
                              double *atom_energy_d, void *stream);
 
 /* The two halves of dp_compute, for an autograd function.  dp_energy_forward
- * computes E (and E_i) and keeps the forward's activations (T, D, fitting-net
- * layers) in the list's scratch.  dp_energy_backward then runs only the
- * adjoint: the fitting-net input gradient, dE/dT, and the backward of the
- * fused step, which recomputes G and G' from the table (G is never stored).
+ * computes E (and E_i) and keeps in the list's scratch what the adjoint
+ * needs: T, the neighbor records, and the fitting net's activations (mixed
+ * precision) or, in FP64 and FP32, where the 256-wide layers and their input
+ * gradients run as one fused kernel with the forward, the gradient at the
+ * first layer.  dp_energy_backward then runs only the rest of the adjoint:
+ * the fitting-net input gradient, dE/dT, and the backward of the fused step,
+ * which recomputes G and G' from the table (G is never stored).  The two
+ * halves give E, F and W bit-identical to one dp_compute call.
  * It writes F = -dE/dx and/or W.  coords_d must be the forward's coordinates.
  * DP_ERR_STATE if no forward of the same mode and precision is kept (any other
  * compute on the list discards it). */

@@ -125,6 +125,11 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
     }
     for (int t = 0; t < kMaxTypes; t++) rt.b4[t] = m->b4[t];
     bool fwd = a.phase != 2, bwd = a.need_forces && a.phase != 1;
+    // FP64 / FP32: every forward runs the fitting net's 256-wide layers, the
+    // energy and their input gradients as one fused kernel (so a backward
+    // that follows, in this call or a later one, starts at dz1); BF16 runs
+    // them as separate GEMMs
+    constexpr bool tail = std::is_same<TA, TR>::value;
     // decides the early end of the candidate scans, and flags moves beyond the list's reach
     launch_displacement(nl, n, a.x, nl->rc_build - m->cfg.rcut, st);
     if (fwd) {
@@ -154,26 +159,47 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
         e.tanh_tab64 = ttab64;
         e = grouped(e, kFitPad, ks * kDdim);
         DP_TIMED("fit_fwd1", st, launch_gemm<TA, TR>(EPI_T1, mr, kFitPad, ks * kDdim, (const TA *)w.D, (const TA *)fw.V1t, e, st));
-        e = Epi{c2, w.y1r, nullptr, nullptr, w.y2r, y2op, w.t2r};
-        e.tanh_tab = ttab;
-        e.tanh_tab64 = ttab64;
-        e = grouped(e, kFitPad, ks * kFitPad);
-        DP_TIMED("fit_fwd2", st, launch_gemm<TA, TR>(EPI_T2, mr, kFitPad, ks * kFitPad, y1in, (const TA *)fw.V2t, e, st));
-        e = Epi{c3, nullptr, nullptr, nullptr, nullptr, nullptr, w.t3r};
-        e.tanh_tab = ttab;
-        e.tanh_tab64 = ttab64;
-        e = grouped(e, kFitPad, ks * kFitPad);
-        DP_TIMED("fit_fwd3", st, launch_gemm<TA, TR>(EPI_T3, mr, kFitPad, ks * kFitPad, y2in, (const TA *)fw.V3t, e, st));
+        if (!tail) {
+            e = Epi{c2, w.y1r, nullptr, nullptr, w.y2r, y2op, w.t2r};
+            e.tanh_tab = ttab;
+            e.tanh_tab64 = ttab64;
+            e = grouped(e, kFitPad, ks * kFitPad);
+            DP_TIMED("fit_fwd2", st, launch_gemm<TA, TR>(EPI_T2, mr, kFitPad, ks * kFitPad, y1in, (const TA *)fw.V2t, e, st));
+            e = Epi{c3, nullptr, nullptr, nullptr, nullptr, nullptr, w.t3r};
+            e.tanh_tab = ttab;
+            e.tanh_tab64 = ttab64;
+            e = grouped(e, kFitPad, ks * kFitPad);
+            DP_TIMED("fit_fwd3", st, launch_gemm<TA, TR>(EPI_T3, mr, kFitPad, ks * kFitPad, y2in, (const TA *)fw.V3t, e, st));
+        }
     }
-    // E_i always; dz3 = w4 (1 - t3^2) when the backward follows
-    launch_energy<TA, TR>(typed ? mr : n, (const TR *)w.y2r, (const TR *)w.t3r, w4, rt, w.e_atom,
-                          bwd ? (TA *)w.dz3o : nullptr, st);
-    if ((s = step_check("fitting_forward", st)) != DP_OK) return s;
+    if (tail && fwd) {
+        // y1 in; E_i and dz1 out
+        TailLaunch tl;
+        if (typed) {
+            tl.ntr = nl->ntypes;
+            for (int t = 0; t <= kMaxTypes; t++) tl.trow[t] = nl->trow[t];
+            tl.ratom = nl->ratom;
+        }
+        tl.nlive = n;
+        for (int t = 0; t < kMaxTypes; t++) tl.b4[t] = m->b4[t];
+        if (m->tanh_on)
+            tl.tanh_tab = std::is_same<TR, double>::value ? (const void *)m->tanh_tab64 : (const void *)m->tanh_tab;
+        if constexpr (std::is_same<TA, TR>::value)
+            DP_TIMED("fit_tail", st, launch_fit_tail<TA>(mr, (const TA *)w.y1r, fw, fb, tl, w.e_atom, (TA *)w.dz1o, (TA *)w.t2r, (TA *)w.dy2r, st));
+        if ((s = step_check("fitting_tail", st)) != DP_OK) return s;
+    } else if (!tail) {
+        // E_i always (also from kept activations); dz3 = w4 (1 - t3^2) when the backward follows
+        launch_energy<TA, TR>(typed ? mr : n, (const TR *)w.y2r, (const TR *)w.t3r, w4, rt, w.e_atom,
+                              bwd ? (TA *)w.dz3o : nullptr, st);
+        if ((s = step_check("fitting_forward", st)) != DP_OK) return s;
+    }
     if (bwd) {
-        e = grouped(Epi{nullptr, nullptr, w4, w.t2r, w.dy2r, w.dz2o, nullptr}, kFitPad, ks * kFitPad);
-        DP_TIMED("fit_bwd3", st, launch_gemm<TA, TR>(EPI_BWD, mr, kFitPad, ks * kFitPad, (const TA *)w.dz3o, (const TA *)fw.V3, e, st));
-        e = grouped(Epi{nullptr, w.dy2r, nullptr, w.y1r, nullptr, w.dz1o, nullptr}, kFitPad, ks * kFitPad);
-        DP_TIMED("fit_bwd2", st, launch_gemm<TA, TR>(EPI_BWD, mr, kFitPad, ks * kFitPad, (const TA *)w.dz2o, (const TA *)fw.V2, e, st));
+        if (!tail) {
+            e = grouped(Epi{nullptr, nullptr, w4, w.t2r, w.dy2r, w.dz2o, nullptr}, kFitPad, ks * kFitPad);
+            DP_TIMED("fit_bwd3", st, launch_gemm<TA, TR>(EPI_BWD, mr, kFitPad, ks * kFitPad, (const TA *)w.dz3o, (const TA *)fw.V3, e, st));
+            e = grouped(Epi{nullptr, w.dy2r, nullptr, w.y1r, nullptr, w.dz1o, nullptr}, kFitPad, ks * kFitPad);
+            DP_TIMED("fit_bwd2", st, launch_gemm<TA, TR>(EPI_BWD, mr, kFitPad, ks * kFitPad, (const TA *)w.dz2o, (const TA *)fw.V2, e, st));
+        }
         e = grouped(Epi{nullptr, nullptr, nullptr, nullptr, w.dDr, nullptr, nullptr}, kDdim, ks * kFitPad);
         DP_TIMED("fit_bwd1", st, launch_gemm<TA, TR>(EPI_LIN, mr, kDdim, ks * kFitPad, (const TA *)w.dz1o, (const TA *)fw.V1, e, st));
         if (PLAIN) {

@@ -288,6 +288,22 @@ struct RowTypes {
 template <typename TA, typename TR>
 void launch_energy(int rows, const TR *y2, const TR *t3, const TR *w4, const RowTypes &rt, double *e_atom,
                    TA *dz3, hipStream_t st);
+// The fused tail of the fitting net (FP64 and FP32): the two 256-wide
+// forward products, E_i, and the two 256-wide input-gradient products, per
+// tile of 64 rows (rows: a multiple of 64).  Reads y1, writes E_i (at the
+// row's atom) and dz1 = dE/d(first layer's pre-activation); t2s and dy2s
+// ([rows][256]) are its scratch.
+struct TailLaunch {
+    int ntr = 0;                            // several types: rows grouped by type (trow), ratom row -> atom
+    int trow[kMaxTypes + 1] = {0, 0, 0, 0, 0};
+    const int *ratom = nullptr;
+    int nlive = 0;                          // one type: rows below nlive are atoms
+    double b4[kMaxTypes] = {0, 0, 0, 0};
+    const void *tanh_tab = nullptr;         // tanh table of the precision, or NULL
+};
+template <typename T>
+void launch_fit_tail(int rows, const T *y1, const FitWeights &fw, const T *fb, const TailLaunch &tl, double *e_atom,
+                     T *dz1, T *t2s, T *dy2s, hipStream_t st);
 template <typename TR>
 void launch_dT(int n, const TR *dD, const TR *T, TR *dT, hipStream_t st);
 // E = sum E_i and W = sum W_i in a fixed order; kFlagNonFinite when either

@@ -392,6 +392,263 @@ __global__ void __launch_bounds__(256) k_energy(int rows, const TR *__restrict__
     if (lane == 0 && atom >= 0) e_atom[atom] = (double)acc + rt.b4[ty];
 }
 
+// ------------------------------------------------ fused fitting-net tail
+// The four 256-wide products of a force step and the energy, per tile of
+// kTailBM rows, in one kernel (FP64 and FP32):
+//   t2 = tanh(y1 V2 + c2), y2 = y1 + t2;   t3 = tanh(y2 V3 + c3);
+//   E_i = (y2 + t3) . w4 + b4,  dz3 = w4 (1 - t3^2);
+//   dy2 = w4 + dz3 V3^T, dz2 = dy2 (1 - t2^2);   dy1 = dy2 + dz2 V2^T,
+//   dz1 = dy1 (1 - y1^2).
+// The tile's current operand (y1, then y2, dz3, dz2) lives in LDS and each
+// product's result in registers; t2 and dy2 wait in scratch arrays for the
+// product that needs them (read back by the lane that wrote them).  Each
+// element of the operand is read back and overwritten in place by the lane
+// whose accumulator holds it.  Four waves: wave w owns rows 16 (w mod 2)
+// .. +16 and columns 128 (w / 2) .. +128 (eight 16 x 16 MFMA tiles).  B (the
+// weights, K-contiguous) streams from L2 in chunks of 64 bytes of K, one
+// chunk ahead in registers, through one LDS buffer (FP64: two barriers per
+// chunk) or two (FP32: one).  Two blocks share a CU, so one block's
+// epilogues and barriers overlap the other's products.  Neither LDS array is
+// padded (two FP64 blocks take all 160 KB): 16-byte granules are
+// XOR-swizzled by row so that the 16 rows a fragment read touches fall in
+// distinct banks.
+constexpr int kTailBM = 32;
+constexpr int kTailThreads = 256;
+constexpr int kTailBChunk = kFitPad * 64;   // bytes of one staged weight chunk
+
+template <typename T>
+struct Tail {
+    static constexpr int ROWB = kFitPad * (int)sizeof(T);   // operand row (bytes)
+    static constexpr int NC = ROWB / 64;                    // 64-byte chunks of K per product
+    static constexpr int NB = sizeof(T) == 8 ? 1 : 2;       // weight buffers
+    static constexpr int LDS = kTailBM * ROWB + NB * kTailBChunk;
+};
+
+// Byte offset of granule g (16 bytes) of operand row r: granules are
+// permuted within each aligned group of 16 by r mod 16.
+__device__ inline int tail_a_off(int r, int rowb, int byte)
+{
+    return r * rowb + ((((byte >> 4) ^ (r & 15)) << 4) | (byte & 15));
+}
+// Byte offset of granule g (0..3) of weight row c within a staged chunk: the
+// four granules of a row permuted by (c / 4) mod 4.
+__device__ inline int tail_b_off(int c, int g) { return c * 64 + ((g ^ ((c >> 2) & 3)) << 4); }
+
+// Rows of the tile (one center type per tile, as the row groups are padded
+// to 128 rows) and where each row's energy goes.
+struct TailArgs {
+    int ntr = 0;
+    int trow[kMaxTypes + 1] = {0, 0, 0, 0, 0};
+    long bstride = 0;   // one type's 256 x 256 weight matrix
+    int vstride = 0;    // one type's block of vectors (kFitB)
+    const int *ratom = nullptr;   // several types: row -> atom (-1: pad)
+    int nlive = 0;                // one type: rows below this are atoms
+    double b4[kMaxTypes] = {0, 0, 0, 0};
+    const void *tanh_tab = nullptr;   // table of the result type, or NULL (native tanh)
+};
+
+constexpr int kTailPieces = kTailBChunk / 16 / kTailThreads;   // 16-byte pieces of a chunk per thread
+
+template <typename T>
+__device__ inline void tail_load_chunk(u4v (&pf)[kTailPieces], const T *__restrict__ Bt, int kc, int tid)
+{
+    // 256 weight rows x 64 bytes: 1024 pieces of 16 bytes
+#pragma unroll
+    for (int r = 0; r < kTailPieces; r++) {
+        int idx = tid + kTailThreads * r;
+        int col = idx >> 2, part = idx & 3;
+        pf[r] = *reinterpret_cast<const u4v *>(reinterpret_cast<const char *>(Bt + (long)col * kFitPad) + kc * 64 +
+                                               part * 16);
+    }
+}
+
+__device__ inline void tail_store_chunk(char *Bbuf, const u4v (&pf)[kTailPieces], int tid)
+{
+#pragma unroll
+    for (int r = 0; r < kTailPieces; r++) {
+        int idx = tid + kTailThreads * r;
+        *reinterpret_cast<u4v *>(Bbuf + tail_b_off(idx >> 2, idx & 3)) = pf[r];
+    }
+}
+
+template <typename T>
+__device__ inline void tail_chunk_mfma(const char *As, const char *Bc, typename MMT<T>::accv (&acc)[8], int kc, int ar,
+                                       int ch, int m, int q)
+{
+    u4v a = *reinterpret_cast<const u4v *>(As + tail_a_off(ar, Tail<T>::ROWB, kc * 64 + q * 16));
+#pragma unroll
+    for (int ct = 0; ct < 8; ct++) {
+        u4v b = *reinterpret_cast<const u4v *>(Bc + tail_b_off(ch * 128 + ct * 16 + m, q));
+        mfma_any<T>(a, b, acc[ct]);
+    }
+}
+
+// acc[ct] = (the tile's operand in As) x Bt^T for this wave's rows and its
+// eight column tiles, over K = 256.  Enters after a barrier that follows the
+// last writes of As and the last reads of Bs; leaves after one that follows
+// the last reads of both.
+template <typename T>
+__device__ inline void tail_gemm(const char *As, char *Bs, const T *__restrict__ Bt,
+                                 typename MMT<T>::accv (&acc)[8], int tid, int rg, int ch, int m, int q)
+{
+    using accv = typename MMT<T>::accv;
+    constexpr int NC = Tail<T>::NC;
+#pragma unroll
+    for (int t = 0; t < 8; t++) acc[t] = accv{0, 0, 0, 0};
+    const int ar = rg * 16 + m;
+    u4v pf[kTailPieces];
+    tail_load_chunk<T>(pf, Bt, 0, tid);
+    if constexpr (Tail<T>::NB == 1) {
+        // one buffer: the chunk in registers goes in once every wave is done
+        // with the previous one
+#pragma unroll 2
+        for (int kc = 0; kc < NC; kc++) {
+            if (kc > 0) __syncthreads();
+            tail_store_chunk(Bs, pf, tid);
+            __syncthreads();
+            if (kc + 1 < NC) tail_load_chunk<T>(pf, Bt, kc + 1, tid);
+            tail_chunk_mfma<T>(As, Bs, acc, kc, ar, ch, m, q);
+        }
+    } else {
+        // two buffers: the next chunk goes into the one read in the previous
+        // iteration (before its barrier)
+        tail_store_chunk(Bs, pf, tid);
+        tail_load_chunk<T>(pf, Bt, 1, tid);
+        __syncthreads();
+#pragma unroll 2
+        for (int kc = 0; kc < NC; kc++) {
+            tail_chunk_mfma<T>(As, Bs + (kc & 1) * kTailBChunk, acc, kc, ar, ch, m, q);
+            if (kc + 1 < NC) {
+                tail_store_chunk(Bs + ((kc + 1) & 1) * kTailBChunk, pf, tid);
+                if (kc + 2 < NC) tail_load_chunk<T>(pf, Bt, kc + 2, tid);
+            }
+            __syncthreads();
+        }
+    }
+    if constexpr (Tail<T>::NB == 1) __syncthreads();
+}
+
+template <typename T, bool TAB>
+__global__ void __launch_bounds__(kTailThreads, 2) k_fit_tail(const T *__restrict__ y1, const T *__restrict__ V2t,
+                                                                const T *__restrict__ V3t, const T *__restrict__ V3,
+                                                                const T *__restrict__ V2, const T *__restrict__ fb,
+                                                                TailArgs ta, double *__restrict__ e_atom,
+                                                                T *__restrict__ dz1, T *__restrict__ t2s,
+                                                                T *__restrict__ dy2s)
+{
+    using accv = typename MMT<T>::accv;
+    constexpr int ROWB = Tail<T>::ROWB;
+    constexpr bool kF64 = std::is_same<T, double>::value;
+    __shared__ __align__(16) char smem[Tail<T>::LDS];
+    char *As = smem;
+    char *Bs = smem + kTailBM * ROWB;
+    // the energy's per-half row partials [2][kTailBM], in the weight buffers
+    // while no product runs
+    double *Ep = reinterpret_cast<double *>(Bs);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int rg = wave & 1, ch = wave >> 1, m = lane & 15, q = lane >> 4;
+    const long row0 = (long)blockIdx.x * kTailBM;
+    int ty = 0;
+    for (int g = 1; g < ta.ntr; g++) ty += row0 >= ta.trow[g] ? 1 : 0;
+    const long wo = ty * ta.bstride;
+    const T *c2 = fb + ty * ta.vstride + kFitPad, *c3 = c2 + kFitPad, *w4 = c3 + kFitPad;
+    // the table switch is a template parameter, so the epilogues' elements
+    // are free of branches and interleave
+    const T *tab = TAB ? reinterpret_cast<const T *>(ta.tanh_tab) : nullptr;
+
+    // the y1 tile into the operand buffer (16-byte granules)
+    constexpr int PR = ROWB / 16;
+    for (int k = tid; k < kTailBM * PR; k += kTailThreads) {
+        int r = k / PR, c = k % PR;
+        *reinterpret_cast<u4v *>(As + tail_a_off(r, ROWB, c * 16)) =
+            *reinterpret_cast<const u4v *>(reinterpret_cast<const char *>(y1 + (row0 + r) * kFitPad) + c * 16);
+    }
+    __syncthreads();
+    // element (ct, i) of this lane: tile row and column (MFMA result layouts
+    // measured on gfx950: FP64 row 4i + q, FP32 row 4q + i; column m)
+    auto erow = [&](int i) { return rg * 16 + (kF64 ? 4 * i + q : 4 * q + i); };
+    auto ecol = [&](int ct) { return ch * 128 + ct * 16 + m; };
+    auto el = [&](int ct, int i) -> T & {
+        return *reinterpret_cast<T *>(As + tail_a_off(erow(i), ROWB, ecol(ct) * (int)sizeof(T)));
+    };
+
+    // t2 (from the first product to the third) and dy2 (third to fourth)
+    // wait in the scratch arrays t2s and dy2s, each element written and read
+    // back by the same lane (registers are taken by the accumulators)
+    auto gel = [&](T *p, int ct, int i) -> T & { return p[(row0 + erow(i)) * kFitPad + ecol(ct)]; };
+    accv acc[8];
+    // y2 = y1 + tanh(y1 V2 + c2)
+    tail_gemm<T>(As, Bs, V2t + wo, acc, tid, rg, ch, m, q);
+#pragma unroll
+    for (int ct = 0; ct < 8; ct++) {
+        T b = c2[ecol(ct)];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            T t = tanh_e((T)acc[ct][i] + b, tab);
+            gel(t2s, ct, i) = t;
+            el(ct, i) += t;
+        }
+    }
+    __syncthreads();
+    // t3 = tanh(y2 V3 + c3); E = (y2 + t3) . w4 + b4; dz3 = w4 (1 - t3^2)
+    tail_gemm<T>(As, Bs, V3t + wo, acc, tid, rg, ch, m, q);
+    T es[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int ct = 0; ct < 8; ct++) {
+        T b = c3[ecol(ct)], w = w4[ecol(ct)];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            T t = tanh_e((T)acc[ct][i] + b, tab);
+            T &o = el(ct, i);
+            es[i] += (o + t) * w;
+            o = w * ((T)1 - t * t);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) es[i] += __shfl_xor(es[i], off);   // the 16 columns of a tile row
+        if (m == 0) Ep[ch * kTailBM + erow(i)] = (double)es[i];
+    }
+    __syncthreads();
+    if (tid < kTailBM) {
+        long row = row0 + tid;
+        int atom = ta.ratom ? ta.ratom[row] : (row < ta.nlive ? (int)row : -1);
+        if (atom >= 0) e_atom[atom] = (double)((T)Ep[tid] + (T)Ep[kTailBM + tid]) + ta.b4[ty];
+    }
+    __syncthreads();
+    // dy2 = w4 + dz3 V3^T; dz2 = dy2 (1 - t2^2)
+    tail_gemm<T>(As, Bs, V3 + wo, acc, tid, rg, ch, m, q);
+#pragma unroll
+    for (int ct = 0; ct < 8; ct++) {
+        T w = w4[ecol(ct)];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            T dy = w + (T)acc[ct][i];
+            T t = gel(t2s, ct, i);
+            gel(dy2s, ct, i) = dy;
+            el(ct, i) = dy * ((T)1 - t * t);
+        }
+    }
+    __syncthreads();
+    // dy1 = dy2 + dz2 V2^T; dz1 = dy1 (1 - y1^2), written out through LDS
+    tail_gemm<T>(As, Bs, V2 + wo, acc, tid, rg, ch, m, q);
+#pragma unroll
+    for (int ct = 0; ct < 8; ct++) {
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            T y = y1[(row0 + erow(i)) * kFitPad + ecol(ct)];
+            el(ct, i) = (gel(dy2s, ct, i) + (T)acc[ct][i]) * ((T)1 - y * y);
+        }
+    }
+    __syncthreads();
+    for (int k = tid; k < kTailBM * PR; k += kTailThreads) {
+        int r = k / PR, c = k % PR;
+        *reinterpret_cast<u4v *>(reinterpret_cast<char *>(dz1 + (row0 + r) * kFitPad) + c * 16) =
+            *reinterpret_cast<const u4v *>(As + tail_a_off(r, ROWB, c * 16));
+    }
+}
+
 // dT[k][c] = sum_{a<M<} dD[a][c] T[k][a] + [c<M<] sum_b dD[c][b] T[k][b]
 // (D[a][b] = sum_k T[k][a] T[k][b]); one wave per atom.  The atom's dD
 // (M< x M) and T (4 x M) are staged in LDS with rows padded by one element,
@@ -546,11 +803,15 @@ static void launch_gemm_t(int epi, int M, int N, int K, const TA *A, const TA *B
 }
 
 // Tile choice: 128 x 128 when M and N allow it (M padded to 128 rows), else
-// 64 x 64.
+// 64 x 64; in FP64, 64 x 128 for the 256-wide output of the first fitting
+// layer, whose 128 x 128 tiles (two per 128 rows) would leave the last of
+// the four rounds of two blocks per CU a third full.
 template <typename TA, typename TR>
 void launch_gemm(int epi, int M, int N, int K, const TA *A, const TA *Bt, const Epi &e, hipStream_t st)
 {
-    if (N % 128 == 0 && M % 128 == 0) launch_gemm_t<TA, TR, 4, 4>(epi, M, N, K, A, Bt, e, st);
+    if (std::is_same<TA, double>::value && N == kFitPad && M % 64 == 0)
+        launch_gemm_t<TA, TR, 2, 4>(epi, M, N, K, A, Bt, e, st);
+    else if (N % 128 == 0 && M % 128 == 0) launch_gemm_t<TA, TR, 4, 4>(epi, M, N, K, A, Bt, e, st);
     else launch_gemm_t<TA, TR, 2, 2>(epi, M, N, K, A, Bt, e, st);
 }
 template void launch_gemm<double, double>(int, int, int, int, const double *, const double *, const Epi &, hipStream_t);
@@ -567,6 +828,33 @@ void launch_energy(int rows, const TR *y2, const TR *t3, const TR *w4, const Row
 template void launch_energy<double, double>(int, const double *, const double *, const double *, const RowTypes &, double *, double *, hipStream_t);
 template void launch_energy<float, float>(int, const float *, const float *, const float *, const RowTypes &, double *, float *, hipStream_t);
 template void launch_energy<__bf16, float>(int, const float *, const float *, const float *, const RowTypes &, double *, __bf16 *, hipStream_t);
+
+template <typename T>
+void launch_fit_tail(int rows, const T *y1, const FitWeights &fw, const T *fb, const TailLaunch &tl, double *e_atom,
+                     T *dz1, T *t2s, T *dy2s, hipStream_t st)
+{
+    TailArgs ta;
+    ta.ntr = tl.ntr;
+    for (int t = 0; t <= kMaxTypes; t++) ta.trow[t] = tl.trow[t];
+    for (int t = 0; t < kMaxTypes; t++) ta.b4[t] = tl.b4[t];
+    ta.bstride = (long)kFitPad * kFitPad;
+    ta.vstride = kFitB;
+    ta.ratom = tl.ratom;
+    ta.nlive = tl.nlive;
+    ta.tanh_tab = tl.tanh_tab;
+    if (tl.tanh_tab)
+        hipLaunchKernelGGL((k_fit_tail<T, true>), dim3(rows / kTailBM), dim3(kTailThreads), 0, st, y1,
+                           (const T *)fw.V2t, (const T *)fw.V3t, (const T *)fw.V3, (const T *)fw.V2, fb, ta, e_atom,
+                           dz1, t2s, dy2s);
+    else
+        hipLaunchKernelGGL((k_fit_tail<T, false>), dim3(rows / kTailBM), dim3(kTailThreads), 0, st, y1,
+                           (const T *)fw.V2t, (const T *)fw.V3t, (const T *)fw.V3, (const T *)fw.V2, fb, ta, e_atom,
+                           dz1, t2s, dy2s);
+}
+template void launch_fit_tail<double>(int, const double *, const FitWeights &, const double *, const TailLaunch &,
+                                      double *, double *, double *, double *, hipStream_t);
+template void launch_fit_tail<float>(int, const float *, const FitWeights &, const float *, const TailLaunch &,
+                                     double *, float *, float *, float *, hipStream_t);
 
 template <typename TR>
 void launch_dT(int n, const TR *dD, const TR *T, TR *dT, hipStream_t st)
