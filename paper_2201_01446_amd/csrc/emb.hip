@@ -35,9 +35,10 @@
 // segments of the same interval.
 //
 // Work distribution (one 64-lane wavefront per atom, neighbor data in LDS):
-//   moments and B: quad q of the wave owns one segment per round, its four
-//   lanes split the segment's neighbors (moments) or the 128 columns (B),
-//   and the quad's partial sums meet in two DPP steps;
+//   moments and B: quad q of the wave owns one segment per round; for the
+//   moments lane l of the quad takes environment column k = l of every
+//   neighbor of the segment, for B the four lanes split the 128 columns and
+//   their partial sums meet in two DPP steps;
 //   contraction into T: each lane owns columns eta = lane and lane + 64;
 //   per-neighbor tail of the backward: each lane owns neighbors.
 
@@ -149,14 +150,16 @@ __device__ int find_segments(const NbrLDS<real> &L, int nn, int lane, int *seg)
 
 constexpr int seg_bytes(int sel) { return ((sel + 1) * 4 + 15) / 16 * 16; }
 
-// Per-wave LDS of the forward: neighbor arrays, T (4 x M), the moments of one
-// round of segments, segment starts.
+// Per-wave LDS of the forward: neighbor arrays, the moments of one round of
+// segments, segment starts; T (4 x M) for the descriptor at the end takes
+// the slice's start once those are dead.
 template <typename real>
 constexpr int fwd_lds_bytes(int sel)
 {
     constexpr int al = (int)sizeof(V4<real>);   // keeps every wave's slice aligned
-    return (nbr_lds_bytes<real>(sel, ENV_FWD) + 4 * kM * (int)sizeof(real) + kSegRound * 24 * (int)sizeof(real) +
-            seg_bytes(sel) + al - 1) / al * al;
+    int b = nbr_lds_bytes<real>(sel, ENV_FWD) + kSegRound * 24 * (int)sizeof(real) + seg_bytes(sel);
+    int t = 4 * kM * (int)sizeof(real);
+    return ((b > t ? b : t) + al - 1) / al * al;
 }
 
 // Per-wave LDS of the backward: neighbor arrays, dT as (dT_0c, .., dT_3c)
@@ -183,8 +186,7 @@ __global__ void __launch_bounds__(256) k_emb_fwd(int natoms, EnvArgs A, const re
     base += wave * fwd_lds_bytes<real>(A.sel);
     NbrLDS<real> L = carve<real>(base, A.sel, ENV_FWD);
     char *p = base + nbr_lds_bytes<real>(A.sel, ENV_FWD);
-    real *Tl = reinterpret_cast<real *>(p);   // 4 x M
-    p += 4 * kM * sizeof(real);
+    real *Tl = reinterpret_cast<real *>(base);   // 4 x M, after the rounds
     real *Ms = reinterpret_cast<real *>(p);   // kSegRound x 24
     p += kSegRound * 24 * sizeof(real);
     int *seg = reinterpret_cast<int *>(p);
@@ -199,37 +201,23 @@ __global__ void __launch_bounds__(256) k_emb_fwd(int natoms, EnvArgs A, const re
     real T0[4] = {0, 0, 0, 0}, T1[4] = {0, 0, 0, 0};   // columns lane, lane + 64
     for (int s0 = 0; s0 < nseg; s0 += kSegRound) {
         int ns = min(kSegRound, nseg - s0);
-        // moments of segment s0 + q: the quad's lanes take every 4th neighbor
-        real M[4][6];
-#pragma unroll
-        for (int k = 0; k < 4; k++)
-#pragma unroll
-            for (int e = 0; e < 6; e++) M[k][e] = 0;
+        // moments of segment s0 + q: lane ql of the quad sums column k = ql
+        // of R over the segment's neighbors, in list order
         if (q < ns) {
+            real Mk[6] = {0, 0, 0, 0, 0, 0};
             int e1 = seg[s0 + q + 1];
-            for (int k = seg[s0 + q] + ql; k < e1; k += 4) {
+            for (int k = seg[s0 + q]; k < e1; k++) {
                 real t = L.t[k];
-                V4<real> R = L.R[k];
+                real r = reinterpret_cast<const real *>(&L.R[k])[ql];
                 real pw = 1;
 #pragma unroll
                 for (int e = 0; e < 6; e++) {
-                    M[0][e] = fma(R.x, pw, M[0][e]);
-                    M[1][e] = fma(R.y, pw, M[1][e]);
-                    M[2][e] = fma(R.z, pw, M[2][e]);
-                    M[3][e] = fma(R.w, pw, M[3][e]);
+                    Mk[e] = fma(r, pw, Mk[e]);
                     pw *= t;
                 }
             }
-        }
 #pragma unroll
-        for (int k = 0; k < 4; k++)
-#pragma unroll
-            for (int e = 0; e < 6; e++) M[k][e] = quad_sum(M[k][e]);
-        if (q < ns && ql == 0) {
-#pragma unroll
-            for (int k = 0; k < 4; k++)
-#pragma unroll
-                for (int e = 0; e < 6; e++) Ms[q * 24 + k * 6 + e] = M[k][e];
+            for (int e = 0; e < 6; e++) Ms[q * 24 + ql * 6 + e] = Mk[e];
         }
         wave_sync();
         // T[k][c] += sum_e a[theta][c][e] M[k][e], lanes over columns; the
@@ -259,7 +247,7 @@ __global__ void __launch_bounds__(256) k_emb_fwd(int natoms, EnvArgs A, const re
                 }
             }
         }
-        wave_sync();   // Ms is rewritten by the next round
+        wave_sync();   // Ms is rewritten by the next round (and the arrays give way to T)
     }
 #pragma unroll
     for (int k = 0; k < 4; k++) {
