@@ -38,10 +38,14 @@ COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters.json")
 
 
 def _kernel_sources_digest():
+    """Digest of every kernel source (csrc/*.hip, csrc/*.h, in name order)."""
+    import glob
     import hashlib
     h = hashlib.sha256()
-    for f in ("emb.hip", "env.h", "emb_common.h", "fit.hip"):
-        with open(os.path.join(ROOT, "paper_2201_01446_amd", "csrc", f), "rb") as fh:
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2201_01446_amd", "csrc", "*.hip")) +
+                    glob.glob(os.path.join(ROOT, "paper_2201_01446_amd", "csrc", "*.h"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
 
