@@ -31,8 +31,12 @@
 // stored at its candidate slot, and a gather after the kernel subtracts from
 // F_j the g_ij of every atom i that lists j (no atomics, a fixed order).
 // Neighbors clamped to the table end form their own segment and get G' = 0.
-// A run split because atoms moved since the list was sorted is simply two
-// segments of the same interval.
+// A run split because atoms moved since the list was sorted gives two
+// segments of the same interval.  In the forward, such duplicates within a
+// round of segments share one representative (the first of the round with
+// that interval), which alone is contracted, with the sum of their moments
+// (the backward's B, computed by the segments' quads in parallel, gains
+// nothing from sharing).
 //
 // Work distribution (one 64-lane wavefront per atom, neighbor data in LDS):
 //   moments and B: quad q of the wave owns one segment per round; for the
@@ -130,6 +134,21 @@ __device__ inline double group_sum(double v)
     return v;
 }
 
+// Representatives of the ns segments of a round starting at s0: lane u < ns
+// returns the first segment v <= u of the round with the same table interval
+// (the clamp bit aside); other lanes return themselves.
+template <typename real>
+__device__ inline int round_reps(const NbrLDS<real> &L, const int *seg, int s0, int ns, int lane)
+{
+    int thu = lane < ns ? (L.th[seg[s0 + lane]] & ~kOobBit) : -1;
+    int rep = lane;
+    for (int v = 0; v < ns; v++) {
+        int thv = __shfl(thu, v);
+        if (v < lane && thv == thu && rep == lane) rep = v;
+    }
+    return rep;
+}
+
 // Starts of the runs of equal interval in the neighbor list: seg[0..nseg-1],
 // seg[nseg] = nn.  Returns nseg (uniform over the wave).
 template <typename real>
@@ -219,23 +238,53 @@ __global__ void __launch_bounds__(256) k_emb_fwd(int natoms, EnvArgs A, const re
 #pragma unroll
             for (int e = 0; e < 6; e++) Ms[q * 24 + ql * 6 + e] = Mk[e];
         }
+        // segments of the round that share an interval: the representative
+        // takes the others' moments (in segment order), and only it is contracted
+        const int rep = round_reps(L, seg, s0, ns, lane);
+        const unsigned long long reps = __ballot(lane < ns && rep == lane);
+        if (reps != ((1ull << ns) - 1ull)) {
+            wave_sync();
+            const bool qrep = q < ns && __shfl(rep, q) == q;   // quad q holds a representative
+            real add[6] = {0, 0, 0, 0, 0, 0};
+            for (int u = 0; u < ns; u++) {
+                int ru = __shfl(rep, u);
+                if (qrep && ru == q && u != q) {
+#pragma unroll
+                    for (int e = 0; e < 6; e++) add[e] += Ms[u * 24 + ql * 6 + e];
+                }
+            }
+            if (qrep) {
+#pragma unroll
+                for (int e = 0; e < 6; e++) Ms[q * 24 + ql * 6 + e] += add[e];
+            }
+        }
         wave_sync();
         // T[k][c] += sum_e a[theta][c][e] M[k][e], lanes over columns; the
-        // coefficients of up to four segments are requested before any is used
-        for (int s1 = 0; s1 < ns; s1 += 4) {
+        // coefficients of up to four representatives are requested before any is used
+        for (unsigned long long left = reps; left;) {
+            int us[4];
+            int nu = 0;
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                us[u] = left ? __builtin_ctzll(left) : -1;
+                if (left) {
+                    left &= left - 1;
+                    nu++;
+                }
+            }
             real a0[4][6], a1[4][6];
 #pragma unroll
             for (int u = 0; u < 4; u++) {
-                if (s1 + u < ns) {
-                    int th = L.th[seg[s0 + s1 + u]] & ~kOobBit;
+                if (u < nu) {
+                    int th = L.th[seg[s0 + us[u]]] & ~kOobBit;
                     coef_col(tab, th, lane, a0[u]);
                     coef_col(tab, th, lane + 64, a1[u]);
                 }
             }
 #pragma unroll
             for (int u = 0; u < 4; u++) {
-                if (s1 + u < ns) {
-                    const real *m = Ms + (s1 + u) * 24;
+                if (u < nu) {
+                    const real *m = Ms + us[u] * 24;
 #pragma unroll
                     for (int k = 0; k < 4; k++)
 #pragma unroll
