@@ -11,7 +11,10 @@ back asynchronously.  The loop then goes straight back to admitting, so
 requests that arrive while others run are taken as soon as a slot frees up,
 and the batches of different slots overlap on the device.  Completion is
 detected with HIP events; a request's latency runs from its arrival to the
-moment its results are on the host.
+moment its results are on the host, split into the wait for a slot (arrival
+to launch) and the service (launch to results on the host).  A request larger
+than a slot's capacity is rejected on its own (its result says why); the
+others are served.
 """
 import ctypes
 import time
@@ -95,6 +98,7 @@ class _Slot:
         self.event = torch.cuda.Event()
         self.busy = False
         self.members = []
+        self.launched = 0.0
 
 
 class Server:
@@ -127,6 +131,7 @@ class Server:
 
     def _launch(self, slot, reqs):
         """reqs: list of (rid, coords[n,3], box)."""
+        slot.launched = time.perf_counter()
         off = 0
         cells = []
         for rid, x, box in reqs:
@@ -146,13 +151,14 @@ class Server:
         slot.members = [(rid, x.shape[0]) for rid, x, _ in reqs]
         slot.busy = True
 
-    def _collect(self, slot, results, done_at):
+    def _collect(self, slot, results, done_at, launched_at):
         now = time.perf_counter()
         off = 0
         for r, (rid, n) in enumerate(slot.members):
             results[rid] = dict(E=float(slot.E_host[r]), W=slot.W_host[r].numpy().copy(),
                                 F=slot.F_host[off:off + n].numpy().copy())
             done_at[rid] = now
+            launched_at[rid] = slot.launched
             off += n
         slot.busy = False
         slot.members = []
@@ -162,25 +168,30 @@ class Server:
         which each request arrives (None: all at once, a closed loop).
         Returns (results by request, stats)."""
         nreq = len(requests)
-        for rid, (x, _) in enumerate(requests):
-            if x.shape[0] > self.slot_atoms:
-                raise ValueError(f"request {rid} ({x.shape[0]} atoms) exceeds the slot capacity {self.slot_atoms}")
         arrivals = np.zeros(nreq) if arrivals is None else np.asarray(arrivals, dtype=np.float64)
         order = np.argsort(arrivals, kind="stable")
-        results, done_at = [None] * nreq, [None] * nreq
+        results, done_at, launched_at = [None] * nreq, [None] * nreq, [None] * nreq
+        # a request no slot can hold is answered at once with the reason
+        rejected = [rid for rid, (x, _) in enumerate(requests) if x.shape[0] > self.slot_atoms]
+        for rid in rejected:
+            results[rid] = dict(error=f"{requests[rid][0].shape[0]} atoms exceed the slot capacity "
+                                      f"{self.slot_atoms}")
+        skip = set(rejected)
+        order = np.array([o for o in order if int(o) not in skip], dtype=np.int64)
+        nserve = len(order)
         waiting = deque()
         nxt = 0
         batch_atoms = []
         t0 = time.perf_counter()
         while True:
             now = time.perf_counter() - t0
-            while nxt < nreq and arrivals[order[nxt]] <= now:
+            while nxt < nserve and arrivals[order[nxt]] <= now:
                 waiting.append(int(order[nxt]))
                 nxt += 1
             progressed = False
             for s in self.slots:   # completions free their slot
                 if s.busy and s.event.query():
-                    self._collect(s, results, done_at)
+                    self._collect(s, results, done_at, launched_at)
                     progressed = True
             for s in self.slots:   # admission in arrival order
                 if s.busy or not waiting:
@@ -195,18 +206,30 @@ class Server:
                 self._launch(s, [(rid, requests[rid][0], requests[rid][1]) for rid in take])
                 batch_atoms.append(atoms)
                 progressed = True
-            if nxt >= nreq and not waiting and not any(s.busy for s in self.slots):
+            if nxt >= nserve and not waiting and not any(s.busy for s in self.slots):
                 break
             if not progressed:
                 time.sleep(2e-5)
         wall = time.perf_counter() - t0
-        lat = np.array([done_at[i] - t0 - arrivals[i] for i in range(nreq)])
-        total_atoms = sum(r[0].shape[0] for r in requests)
-        stats = dict(requests=nreq, atoms=int(total_atoms), wall_s=wall, atoms_per_s=total_atoms / wall,
-                     p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
-                     mean_ms=float(lat.mean() * 1e3), batches=len(batch_atoms),
+        served = [int(i) for i in order]
+        lat = np.array([done_at[i] - t0 - arrivals[i] for i in served])
+        wait = np.array([launched_at[i] - t0 - arrivals[i] for i in served])
+        size = np.array([requests[i][0].shape[0] for i in served])
+        total_atoms = int(size.sum())
+        stats = dict(requests=nreq, rejected=len(rejected), atoms=total_atoms, wall_s=wall,
+                     atoms_per_s=total_atoms / wall, batches=len(batch_atoms),
                      mean_batch_atoms=float(np.mean(batch_atoms)) if batch_atoms else 0.0,
                      slot_atoms=self.slot_atoms, slots=len(self.slots))
+        if served:
+            p99 = np.percentile(lat, 99)
+            tail = lat >= p99
+            stats.update(p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(p99 * 1e3),
+                         mean_ms=float(lat.mean() * 1e3), mean_wait_ms=float(wait.mean() * 1e3),
+                         mean_service_ms=float((lat - wait).mean() * 1e3),
+                         # the slowest 1 %: what their latency was made of
+                         tail_wait_ms=float(wait[tail].mean() * 1e3),
+                         tail_service_ms=float((lat - wait)[tail].mean() * 1e3),
+                         tail_mean_atoms=float(size[tail].mean()), mean_atoms=float(size.mean()))
         return results, stats
 
 

@@ -146,25 +146,45 @@ def test_autograd_500k_fp32_sampled(P, model, cu_cfg, cu_params):
 # -------------------------------------------------------------------- NVE
 
 def test_nve_fp32_energy_conservation(P, cu_cfg):
-    """FP32 forces, FP64 integration and reductions.  The same 50-step
-    trajectory in FP64 gives the integrator's own energy error; the FP32 run
-    may exceed it only by the FP32 rounding of the potential energy (the
-    output weights are scaled up so forces are of copper's size, which also
-    puts a large constant into E)."""
+    """FP32 forces, FP64 integration and reductions.  At any step the FP32
+    run's total-energy change is the integrator's (measured on the same
+    trajectory in FP64) plus the FP32 rounding of the potential energy at the
+    two configurations compared, delta(x) = E_FP32(x) - E_FP64(x), which the
+    test measures directly at every 10-step snapshot of the FP32 trajectory:
+        |Etot32(t) - Etot32(0)| <= 1.1 |Etot64(t) - Etot64(0)| + |delta(t)| + |delta(0)|
+    (the 10 % covers the small difference between the two trajectories).
+    The output weights are scaled up so forces are of copper's size."""
     p = synth.model_params(cu_cfg)
     synth.split_params(cu_cfg, p)["w4"][:] *= 2000.0
     m = P.Model(cu_cfg, p).tabulate(S_MAX, H, TAIL, H_TAIL)
     x0, box = synth.copper(4, 0.05, 3)
     v0 = synth.maxwell_boltzmann(len(x0), 330.0, seed=4)
-    dev_e = {}
+
+    def rounding(nl, x):
+        e = [float(P.compute(m, nl, x, precision=q, forces=False, virial=False)["E"].item())
+             for q in (P.FP32, P.FP64)]
+        return abs(e[0] - e[1])
+
+    et, delta, ke0 = {}, [], None
     for prec in (P.FP64, P.FP32):
         x, v = dev(x0), dev(v0)
         nl = P.NeighborList(m, x, box)
-        th = P.nve_run(m, nl, x, v, box, synth.M_CU, 1.0, 50, rebuild_every=10, precision=prec).cpu().numpy()
-        et = th.sum(1)
-        dev_e[prec] = (np.max(np.abs(et - et[0])), abs(th[0, 0]), th[0, 1])
-    d64, pe, ke = dev_e[P.FP64]
-    d32 = dev_e[P.FP32][0]
-    print(f"nve: max |E - E0| fp64 {d64:.3g} eV, fp32 {d32:.3g} eV, |PE| {pe:.3g} eV, KE0 {ke:.3g} eV")
-    assert d64 < 1e-3 * ke
-    assert d32 <= d64 + 2e-7 * pe
+        tot = []
+        for chunk in range(5):
+            if prec == P.FP32:
+                delta.append(rounding(nl, x))
+            th = P.nve_run(m, nl, x, v, box, synth.M_CU, 1.0, 10, rebuild_every=10, precision=prec).cpu().numpy()
+            if chunk == 0:
+                tot.append(th[0].sum())
+                ke0 = th[0, 1]
+            tot.append(th[-1].sum())
+        if prec == P.FP32:
+            delta.append(rounding(nl, x))
+        et[prec] = np.array(tot)   # total energy at steps 0, 10, ..., 50
+    d64 = np.abs(et[P.FP64] - et[P.FP64][0])
+    d32 = np.abs(et[P.FP32] - et[P.FP32][0])
+    delta = np.array(delta)
+    print(f"nve: |dEtot| fp64 {d64}, fp32 {d32}, FP32 rounding of PE {delta}, KE0 {ke0:.3g} eV")
+    assert np.max(d64) < 1e-3 * ke0
+    for t in range(1, len(d32)):
+        assert d32[t] <= 1.1 * d64[t] + delta[t] + delta[0] + 1e-12, t

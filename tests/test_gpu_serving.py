@@ -161,3 +161,25 @@ def test_server_closed_loop_and_poisson(P, model):
         assert res2[k]["E"] == res[k]["E"]
         np.testing.assert_array_equal(res2[k]["F"], res[k]["F"])
     assert st2["p99_ms"] >= st2["p50_ms"] > 0
+
+
+def test_server_rejects_oversize_request_alone(P, model):
+    """A request larger than every slot is answered with an error of its own;
+    the requests around it are served, with the results they have alone, and
+    the latency split (wait for a slot + service) adds up."""
+    from paper_2201_01446_amd.serve import Server
+    reqs = [r[:2] for r in synth.serving_stream(8, 32, 1500, seed=synth.SEED_SERVING + 7)]
+    srv = Server(model, P.FP32, slots=2, hbm_budget=2 * 200 << 20)
+    big = synth.copper(10, 0.05, 5)   # 4,000 atoms
+    assert srv.slot_atoms < 4000 and max(x.shape[0] for x, _ in reqs) <= srv.slot_atoms
+    reqs.insert(3, big)
+    res, st = srv.run(reqs)
+    print("with an oversize request:", st)
+    assert st["rejected"] == 1 and "exceed" in res[3]["error"]
+    assert st["atoms"] == sum(x.shape[0] for x, _ in reqs) - 4000
+    for k in (0, 4, len(reqs) - 1):
+        alone, _ = run_batch(P, model, [reqs[k]], P.FP32)
+        assert res[k]["E"] == alone[0]["E"]
+        np.testing.assert_array_equal(res[k]["F"], alone[0]["F"])
+    assert abs(st["mean_wait_ms"] + st["mean_service_ms"] - st["mean_ms"]) <= 1e-6 * st["mean_ms"]
+    assert st["tail_wait_ms"] >= 0 and st["tail_service_ms"] > 0
