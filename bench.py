@@ -629,8 +629,9 @@ def serving(P, model, nreq):
     _, closed = srv.run(reqs)
     rate = 0.7 * nreq / closed["wall_s"]
     _, pois = srv.run(reqs, poisson_arrivals(nreq, rate, seed=synth.SEED_SERVING + 1))
-    keep = ("atoms_per_s", "p50_ms", "p99_ms", "mean_ms", "batches", "mean_batch_atoms", "wall_s")
-    return {"requests": nreq, "atoms": closed["atoms"], "slots": closed["slots"],
+    keep = ("atoms_per_s", "p50_ms", "p99_ms", "mean_ms", "mean_wait_ms", "mean_service_ms", "tail_wait_ms",
+            "tail_service_ms", "tail_mean_atoms", "mean_atoms", "batches", "mean_batch_atoms", "wall_s")
+    return {"requests": nreq, "rejected": closed["rejected"], "atoms": closed["atoms"], "slots": closed["slots"],
             "slot_atoms": closed["slot_atoms"], "precision": "fp32",
             "closed_loop": {k: round(closed[k], 4) for k in keep},
             "poisson": dict({k: round(pois[k], 4) for k in keep}, rate_req_per_s=round(rate, 2)),
