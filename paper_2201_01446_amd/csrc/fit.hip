@@ -803,14 +803,16 @@ static void launch_gemm_t(int epi, int M, int N, int K, const TA *A, const TA *B
 }
 
 // Tile choice: 128 x 128 when M and N allow it (M padded to 128 rows), else
-// 64 x 64; in FP64, 64 x 128 for the 256-wide output of the first fitting
-// layer, whose 128 x 128 tiles (two per 128 rows) would leave the last of
-// the four rounds of two blocks per CU a third full.
+// 64 x 64.  FP64 takes 64 x 64 tiles for the first fitting layer and its
+// input gradient too: four blocks (16 waves) per CU instead of two, and
+// many more tiles for the last round (measured on 108,000 atoms: first layer
+// 2.35 ms with 64 x 128 tiles, 2.65 with 128 x 128, 2.11 with 64 x 64); the
+// FP32 ones keep 128 x 128 and their LDS-staged epilogue.
 template <typename TA, typename TR>
 void launch_gemm(int epi, int M, int N, int K, const TA *A, const TA *Bt, const Epi &e, hipStream_t st)
 {
-    if (std::is_same<TA, double>::value && N == kFitPad && M % 64 == 0)
-        launch_gemm_t<TA, TR, 2, 4>(epi, M, N, K, A, Bt, e, st);
+    if (std::is_same<TA, double>::value && (N == kFitPad || N == kDdim) && M % 64 == 0)
+        launch_gemm_t<TA, TR, 2, 2>(epi, M, N, K, A, Bt, e, st);
     else if (N % 128 == 0 && M % 128 == 0) launch_gemm_t<TA, TR, 4, 4>(epi, M, N, K, A, Bt, e, st);
     else launch_gemm_t<TA, TR, 2, 2>(epi, M, N, K, A, Bt, e, st);
 }
