@@ -403,8 +403,10 @@ __global__ void __launch_bounds__(256) k_energy(int rows, const TR *__restrict__
 // product's result in registers; t2 and dy2 wait in scratch arrays for the
 // product that needs them (read back by the lane that wrote them).  Each
 // element of the operand is read back and overwritten in place by the lane
-// whose accumulator holds it.  Four waves: wave w owns rows 16 (w mod 2)
-// .. +16 and columns 128 (w / 2) .. +128 (eight 16 x 16 MFMA tiles).  B (the
+// whose accumulator holds it.  Eight waves: wave w owns rows 16 (w mod 2)
+// .. +16 and columns 64 (w / 2) .. +64 (four 16 x 16 MFMA tiles), so two
+// blocks give four waves per SIMD (measured faster than four waves per
+// block: FP64 1.34 -> 1.32 ms, FP32 0.63 -> 0.58 ms on 108,000 atoms).  B (the
 // weights, K-contiguous) streams from L2 in chunks of 64 bytes of K, one
 // chunk ahead in registers, through one LDS buffer (FP64: two barriers per
 // chunk) or two (FP32: one).  Two blocks share a CU, so one block's
@@ -413,7 +415,9 @@ __global__ void __launch_bounds__(256) k_energy(int rows, const TR *__restrict__
 // XOR-swizzled by row so that the 16 rows a fragment read touches fall in
 // distinct banks.
 constexpr int kTailBM = 32;
-constexpr int kTailThreads = 256;
+constexpr int kTailThreads = 512;
+constexpr int kTailCG = kTailThreads / 64 / 2;   // column groups (waves per 16 rows)
+constexpr int kTailCT = 16 / kTailCG;            // 16 x 16 column tiles per wave
 constexpr int kTailBChunk = kFitPad * 64;   // bytes of one staged weight chunk
 
 template <typename T>
@@ -472,13 +476,13 @@ __device__ inline void tail_store_chunk(char *Bbuf, const u4v (&pf)[kTailPieces]
 }
 
 template <typename T>
-__device__ inline void tail_chunk_mfma(const char *As, const char *Bc, typename MMT<T>::accv (&acc)[8], int kc, int ar,
+__device__ inline void tail_chunk_mfma(const char *As, const char *Bc, typename MMT<T>::accv (&acc)[kTailCT], int kc, int ar,
                                        int ch, int m, int q)
 {
     u4v a = *reinterpret_cast<const u4v *>(As + tail_a_off(ar, Tail<T>::ROWB, kc * 64 + q * 16));
 #pragma unroll
-    for (int ct = 0; ct < 8; ct++) {
-        u4v b = *reinterpret_cast<const u4v *>(Bc + tail_b_off(ch * 128 + ct * 16 + m, q));
+    for (int ct = 0; ct < kTailCT; ct++) {
+        u4v b = *reinterpret_cast<const u4v *>(Bc + tail_b_off(ch * 16 * kTailCT + ct * 16 + m, q));
         mfma_any<T>(a, b, acc[ct]);
     }
 }
@@ -489,12 +493,12 @@ __device__ inline void tail_chunk_mfma(const char *As, const char *Bc, typename 
 // the last reads of both.
 template <typename T>
 __device__ inline void tail_gemm(const char *As, char *Bs, const T *__restrict__ Bt,
-                                 typename MMT<T>::accv (&acc)[8], int tid, int rg, int ch, int m, int q)
+                                 typename MMT<T>::accv (&acc)[kTailCT], int tid, int rg, int ch, int m, int q)
 {
     using accv = typename MMT<T>::accv;
     constexpr int NC = Tail<T>::NC;
 #pragma unroll
-    for (int t = 0; t < 8; t++) acc[t] = accv{0, 0, 0, 0};
+    for (int t = 0; t < kTailCT; t++) acc[t] = accv{0, 0, 0, 0};
     const int ar = rg * 16 + m;
     u4v pf[kTailPieces];
     tail_load_chunk<T>(pf, Bt, 0, tid);
@@ -529,7 +533,7 @@ __device__ inline void tail_gemm(const char *As, char *Bs, const T *__restrict__
 }
 
 template <typename T, bool TAB>
-__global__ void __launch_bounds__(kTailThreads, 2) k_fit_tail(const T *__restrict__ y1, const T *__restrict__ V2t,
+__global__ void __launch_bounds__(kTailThreads, kTailThreads / 128) k_fit_tail(const T *__restrict__ y1, const T *__restrict__ V2t,
                                                                 const T *__restrict__ V3t, const T *__restrict__ V3,
                                                                 const T *__restrict__ V2, const T *__restrict__ fb,
                                                                 TailArgs ta, double *__restrict__ e_atom,
@@ -546,7 +550,7 @@ __global__ void __launch_bounds__(kTailThreads, 2) k_fit_tail(const T *__restric
     // while no product runs
     double *Ep = reinterpret_cast<double *>(Bs);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int rg = wave & 1, ch = wave >> 1, m = lane & 15, q = lane >> 4;
+    const int rg = wave & 1, ch = wave >> 1, m = lane & 15, q = lane >> 4;   // ch: column group
     const long row0 = (long)blockIdx.x * kTailBM;
     int ty = 0;
     for (int g = 1; g < ta.ntr; g++) ty += row0 >= ta.trow[g] ? 1 : 0;
@@ -567,7 +571,7 @@ __global__ void __launch_bounds__(kTailThreads, 2) k_fit_tail(const T *__restric
     // element (ct, i) of this lane: tile row and column (MFMA result layouts
     // measured on gfx950: FP64 row 4i + q, FP32 row 4q + i; column m)
     auto erow = [&](int i) { return rg * 16 + (kF64 ? 4 * i + q : 4 * q + i); };
-    auto ecol = [&](int ct) { return ch * 128 + ct * 16 + m; };
+    auto ecol = [&](int ct) { return ch * 16 * kTailCT + ct * 16 + m; };
     auto el = [&](int ct, int i) -> T & {
         return *reinterpret_cast<T *>(As + tail_a_off(erow(i), ROWB, ecol(ct) * (int)sizeof(T)));
     };
@@ -576,11 +580,11 @@ __global__ void __launch_bounds__(kTailThreads, 2) k_fit_tail(const T *__restric
     // wait in the scratch arrays t2s and dy2s, each element written and read
     // back by the same lane (registers are taken by the accumulators)
     auto gel = [&](T *p, int ct, int i) -> T & { return p[(row0 + erow(i)) * kFitPad + ecol(ct)]; };
-    accv acc[8];
+    accv acc[kTailCT];
     // y2 = y1 + tanh(y1 V2 + c2)
     tail_gemm<T>(As, Bs, V2t + wo, acc, tid, rg, ch, m, q);
 #pragma unroll
-    for (int ct = 0; ct < 8; ct++) {
+    for (int ct = 0; ct < kTailCT; ct++) {
         T b = c2[ecol(ct)];
 #pragma unroll
         for (int i = 0; i < 4; i++) {
@@ -594,7 +598,7 @@ __global__ void __launch_bounds__(kTailThreads, 2) k_fit_tail(const T *__restric
     tail_gemm<T>(As, Bs, V3t + wo, acc, tid, rg, ch, m, q);
     T es[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int ct = 0; ct < 8; ct++) {
+    for (int ct = 0; ct < kTailCT; ct++) {
         T b = c3[ecol(ct)], w = w4[ecol(ct)];
 #pragma unroll
         for (int i = 0; i < 4; i++) {
@@ -614,13 +618,16 @@ __global__ void __launch_bounds__(kTailThreads, 2) k_fit_tail(const T *__restric
     if (tid < kTailBM) {
         long row = row0 + tid;
         int atom = ta.ratom ? ta.ratom[row] : (row < ta.nlive ? (int)row : -1);
-        if (atom >= 0) e_atom[atom] = (double)((T)Ep[tid] + (T)Ep[kTailBM + tid]) + ta.b4[ty];
+        T e = (T)Ep[tid];
+#pragma unroll
+        for (int g = 1; g < kTailCG; g++) e += (T)Ep[g * kTailBM + tid];
+        if (atom >= 0) e_atom[atom] = (double)e + ta.b4[ty];
     }
     __syncthreads();
     // dy2 = w4 + dz3 V3^T; dz2 = dy2 (1 - t2^2)
     tail_gemm<T>(As, Bs, V3 + wo, acc, tid, rg, ch, m, q);
 #pragma unroll
-    for (int ct = 0; ct < 8; ct++) {
+    for (int ct = 0; ct < kTailCT; ct++) {
         T w = w4[ecol(ct)];
 #pragma unroll
         for (int i = 0; i < 4; i++) {
@@ -634,7 +641,7 @@ __global__ void __launch_bounds__(kTailThreads, 2) k_fit_tail(const T *__restric
     // dy1 = dy2 + dz2 V2^T; dz1 = dy1 (1 - y1^2), written out through LDS
     tail_gemm<T>(As, Bs, V2 + wo, acc, tid, rg, ch, m, q);
 #pragma unroll
-    for (int ct = 0; ct < 8; ct++) {
+    for (int ct = 0; ct < kTailCT; ct++) {
 #pragma unroll
         for (int i = 0; i < 4; i++) {
             T y = y1[(row0 + erow(i)) * kFitPad + ecol(ct)];
