@@ -94,6 +94,8 @@ def parse():
     ap.add_argument("--water-only", action="store_true",
                     help="run only the water section (--steps timed steps) and print it (for profiling)")
     ap.add_argument("--ablation-steps", type=int, default=10)
+    ap.add_argument("--rebuild-every", type=int, default=10,
+                    help="neighbor-list rebuild cadence in steps (the workload's is 10)")
     ap.add_argument("--stride-steps", type=int, default=20)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one elementwise negation over this many MiB (reads and writes it once): "
@@ -108,13 +110,14 @@ REBUILD = 10
 
 
 def run_nve(P, model, x0, v0, box, steps, warmup, precision, mode=0, keep=False, types=None, mass=63.546, dt=1.0):
+    rebuild = REBUILD
     import torch
     x = torch.tensor(x0, dtype=torch.float64, device="cuda")
     v = torch.tensor(v0, dtype=torch.float64, device="cuda")
     td = None if types is None else torch.tensor(types, dtype=torch.int32, device="cuda")
     nl = P.NeighborList(model, x, box, skin=2.0, types=td)
     if warmup:
-        P.nve_run(model, nl, x, v, box, mass, dt, warmup, rebuild_every=REBUILD, precision=precision, mode=mode, types=td)
+        P.nve_run(model, nl, x, v, box, mass, dt, warmup, rebuild_every=rebuild, precision=precision, mode=mode, types=td)
     torch.cuda.synchronize()
     from paper_2201_01446_amd import _lib
     _lib.timers_read()
@@ -124,7 +127,7 @@ def run_nve(P, model, x0, v0, box, steps, warmup, precision, mode=0, keep=False,
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     t0.record()
-    th = P.nve_run(model, nl, x, v, box, mass, dt, steps, rebuild_every=REBUILD, precision=precision, mode=mode, types=td)
+    th = P.nve_run(model, nl, x, v, box, mass, dt, steps, rebuild_every=rebuild, precision=precision, mode=mode, types=td)
     t1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
@@ -199,6 +202,8 @@ def final_state(P, model, res, precision):
 
 def main():
     args = parse()
+    global REBUILD
+    REBUILD = args.rebuild_every
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the per-GPU share is the "
               "108,000-atom kernel measured at --gpus 1.", file=sys.stderr)
@@ -297,7 +302,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic: seeded FCC Cu + Gaussian displacements, seeded random weights",
         "config": {"workload": f"Cu FCC {args.ncell}^3 cells ({N} atoms), sigma 0.05 A, 330 K, NVE dt 1 fs, "
-                               "nlist skin 2 A rebuilt every 10 steps, compressed (stride 0.01, tail 0.1)",
+                               f"nlist skin 2 A rebuilt every {REBUILD} steps, compressed (stride 0.01, tail 0.1)",
                    "natoms": N, "precision": "fp64", "mode": "compressed"},
         "ns_per_day": head["ns_per_day"],
         "roofline": head["roofline"],
