@@ -277,9 +277,20 @@ def main():
         summary[name] = {"value": round(vp, 1), "ms_per_step": round(r["ms"] / Kp, 4), "steps": Kp,
                          "kernels": {k: round(t[0] / max(t[1], 1), 4) for k, t in r["kernels"].items()},
                          "speedup_compressed_vs_plain": round(comp / vp, 3) if comp else None}
-        tr = plain_traffic(r["kernels"], "f64" if name.endswith("64") else "f32", Kp)
+        tag = "f64" if name.endswith("64") else "f32"
+        tr = plain_traffic(r["kernels"], tag, Kp)
         if tr:
             summary[name]["roofline"] = tr
+        sb = plain_step_bytes(tag)
+        if sb:
+            # the whole step against HBM: how slack this denominator is, and
+            # the compressed path's advantage over a plain path at its bound
+            bound_ms = sb / (HBM_PEAK_GBS * 1e9) * 1e3
+            summary[name]["step_hbm_bytes"] = sb
+            summary[name]["step_hbm_bound_ms"] = round(bound_ms, 3)
+            summary[name]["frac_of_step_hbm_bound"] = round(bound_ms / (r["ms"] / Kp), 4)
+            if comp:
+                summary[name]["speedup_at_plain_hbm_bound"] = round(bound_ms / (N / comp * 1e3), 3)
     del runs, plain
     gc.collect()
 
@@ -345,6 +356,19 @@ def main():
             if isinstance(tgt, dict):
                 tgt["accuracy_gate_pass"] = g["pass"]
     print(json.dumps(out))
+
+
+def plain_step_bytes(tag):
+    """The plain path's HBM bytes per step from the committed counters (None
+    when there are none for these sources)."""
+    try:
+        with open(COUNTERS) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("sources_digest") != _kernel_sources_digest():
+        return None
+    return rec.get("plain_step_bytes", {}).get(tag)
 
 
 def plain_traffic(kern, tag, steps):
