@@ -24,9 +24,16 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
 
 
+# per translation unit: the GEMM keeps MFMA results in VGPRs (with
+# accumulation registers the compiler copied the FP64 accumulators out and
+# back on every K stage); the other MFMA kernel, the fused fitting tail,
+# gets VGPR results without it
+FILE_FLAGS = {"gemm.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + FLAGS + FILE_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     p = subprocess.run(cmd, capture_output=True, text=True)
     msgs = "\n".join(l for l in (p.stdout + p.stderr).splitlines()
                      if "packed-fp32-ops" not in l)

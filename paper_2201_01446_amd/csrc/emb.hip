@@ -431,7 +431,8 @@ __global__ void __launch_bounds__(256) k_emb_bwd(int natoms, EnvArgs A, const re
             int th = L.th[seg[s0 + q]] & ~kOobBit;
             // FP64: every coefficient load of the segment in flight at once;
             // FP32: four (measured fastest for each)
-#pragma unroll(sizeof(real) == 8 ? kM / 4 : 4)
+            constexpr int kLoadsInFlight = sizeof(real) == 8 ? kM / 4 : 4;
+#pragma unroll kLoadsInFlight
             for (int m = 0; m < kM / 4; m++) {
                 int c = 4 * m + ql;
                 V4<real> d = dTl[c];
