@@ -102,12 +102,30 @@ dp_status upload_fit(FitWeights &w, const std::vector<double> *mats, int prec)
             DP_HIP(hipMemcpy(*dst[k], b.data(), 3 * n * 2, hipMemcpyHostToDevice));
         }
     }
+    if (prec == DP_FP64 || prec == DP_FP32) {
+        // V1tp: the columns of V1t in the order k' = b M< + a of the operand
+        // that the first layer forms from T
+        const std::vector<double> &m = mats[1];
+        size_t rows = m.size() / kDdim;
+        std::vector<double> pm(m.size());
+        for (size_t r = 0; r < rows; r++)
+            for (int a = 0; a < kMlt; a++)
+                for (int b = 0; b < kM; b++) pm[r * kDdim + (size_t)b * kMlt + a] = m[r * kDdim + (size_t)a * kM + b];
+        if (prec == DP_FP64) {
+            DP_HIP(hipMalloc(&w.V1tp, pm.size() * 8));
+            DP_HIP(hipMemcpy(w.V1tp, pm.data(), pm.size() * 8, hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> f(pm.begin(), pm.end());
+            DP_HIP(hipMalloc(&w.V1tp, f.size() * 4));
+            DP_HIP(hipMemcpy(w.V1tp, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+        }
+    }
     return DP_OK;
 }
 
 void free_fit(FitWeights &w)
 {
-    void *p[6] = {w.V1, w.V1t, w.V2, w.V2t, w.V3, w.V3t};
+    void *p[7] = {w.V1, w.V1t, w.V2, w.V2t, w.V3, w.V3t, w.V1tp};
     for (void *q : p)
         if (q) (void)hipFree(q);
     w = FitWeights{};

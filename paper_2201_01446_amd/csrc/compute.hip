@@ -130,6 +130,10 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
     // that follows, in this call or a later one, starts at dz1); BF16 runs
     // them as separate GEMMs
     constexpr bool tail = std::is_same<TA, TR>::value;
+    // FP32 / FP64 compressed forward: the first fitting layer forms D = T<^T T
+    // from T as it stages its operand, and the embedding kernel writes no D
+    // (unless the caller asks for D)
+    const bool dfuse = tail && !PLAIN && a.mode == DP_COMPRESSED && !a.D_out;
     // decides the early end of the candidate scans, and flags moves beyond the list's reach
     launch_displacement(nl, n, a.x, nl->rc_build - m->cfg.rcut, st);
     if (fwd) {
@@ -137,14 +141,18 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
             bool tab = a.mode == DP_TAB_UNFUSED;
             if ((s = plain_forward<TR, TA>(m, a.nl, n, a.x, w.T, w.D, a.nnei_out, st, tab)) != DP_OK) return s;
         } else if (a.mode == DP_COMPRESSED) {
-            DP_TIMED("emb_fwd", st, launch_emb_fwd(m, a.nl, n, a.x, a.precision, w.T, w.D, w.rec, w.rcnt, a.nnei_out, a.nseg_out, st));
+            DP_TIMED("emb_fwd", st, launch_emb_fwd(m, a.nl, n, a.x, a.precision, w.T, dfuse ? nullptr : w.D, w.rec, w.rcnt, a.nnei_out, a.nseg_out, st));
             if ((s = step_check("emb_fwd", st)) != DP_OK) return s;
         } else {
             bool pad = a.mode == DP_FUSED_PADDED;
             DP_TIMED("emb_fwd_pn", st, launch_emb_fwd_pn(m, a.nl, n, a.x, a.precision, w.T, w.D, w.rec, w.rcnt, pad, a.nnei_out, st));
             if ((s = step_check("emb_fwd", st)) != DP_OK) return s;
         }
-        if (a.T_out) launch_to_double<TR>((long)n * 4 * kM, (const TR *)w.T, a.T_out, st);
+        if (a.T_out) {
+            // the compressed embedding kernel stores T by column
+            if (!PLAIN && a.mode == DP_COMPRESSED) launch_tcol_to_double<TR>(n, (const TR *)w.T, a.T_out, st);
+            else launch_to_double<TR>((long)n * 4 * kM, (const TR *)w.T, a.T_out, st);
+        }
         if (a.D_out) launch_op_to_double<TA>(n, kDdim, (const TA *)w.D, typed ? nl->row : nullptr, a.D_out, st);
         // the fitting net's tanh: native, or the table (in the epilogue's precision) when enabled
         const float *ttab = m->tanh_on ? m->tanh_tab : nullptr;
@@ -158,7 +166,15 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
         e.tanh_tab = ttab;
         e.tanh_tab64 = ttab64;
         e = grouped(e, kFitPad, ks * kDdim);
-        DP_TIMED("fit_fwd1", st, launch_gemm<TA, TR>(EPI_T1, mr, kFitPad, ks * kDdim, (const TA *)w.D, (const TA *)fw.V1t, e, st));
+        if (dfuse) {
+            e.dt_T = w.T;
+            e.dt_ratom = typed ? nl->ratom : nullptr;
+            e.dt_nlive = n;
+            if constexpr (std::is_same<TA, TR>::value)
+                DP_TIMED("fit_fwd1", st, launch_gemm_dt<TA, TR>(mr, kFitPad, (const TA *)fw.V1tp, e, st));
+        } else {
+            DP_TIMED("fit_fwd1", st, launch_gemm<TA, TR>(EPI_T1, mr, kFitPad, ks * kDdim, (const TA *)w.D, (const TA *)fw.V1t, e, st));
+        }
         if (!tail) {
             e = Epi{c2, w.y1r, nullptr, nullptr, w.y2r, y2op, w.t2r};
             e.tanh_tab = ttab;

@@ -52,6 +52,9 @@ struct TableInfo {
 struct FitWeights {
     void *V1 = nullptr, *V2 = nullptr, *V3 = nullptr;
     void *V1t = nullptr, *V2t = nullptr, *V3t = nullptr;
+    // V1t with its columns in the order k' = b M< + a of the D operand formed
+    // from T (column a M + b of V1t at k'); FP32 and FP64
+    void *V1tp = nullptr;
 };
 
 }  // namespace dp
@@ -273,9 +276,19 @@ struct Epi {
     int trow[dp::kMaxTypes + 1] = {0, 0, 0, 0, 0};
     long bstride = 0;
     int vstride = 0;
+    // launch_gemm_dt: T (TA[atoms][kM][4], by column) whose D = T<^T T is the A operand,
+    // the atom of each row (several types; -1: padding) or, with one type,
+    // the rows below dt_nlive are the atoms
+    const void *dt_T = nullptr;
+    const int *dt_ratom = nullptr;
+    int dt_nlive = 0;
 };
 template <typename TA, typename TR>
 void launch_gemm(int epi, int M, int N, int K, const TA *A, const TA *Bt, const Epi &e, hipStream_t st);
+// y1 = tanh(D V1 + c1) (the EPI_T1 epilogue) with D formed from e.dt_T as the
+// operand is staged; Bt is V1tp, K = kDdim (FP32, FP64)
+template <typename TA, typename TR>
+void launch_gemm_dt(int M, int N, const TA *Bt, const Epi &e, hipStream_t st);
 // E_i and dz3 for rows [0, rows); several types: w4 and b4 of the row's
 // type group (Epi trow / vstride), E written to e_atom[ratom[row]] (pad rows
 // skipped); one type: e_atom[row].
@@ -312,6 +325,9 @@ void launch_reduce(int n, const double *e_atom, const double *w_atom, double *pa
                    double *virial, int *flags, hipStream_t st);
 template <typename T>
 void launch_to_double(long n, const T *a, double *b, hipStream_t st);
+// T stored by column (n atoms x kM columns of (T_0c, .., T_3c)) to FP64 [n][4][kM]
+template <typename T>
+void launch_tcol_to_double(int n, const T *a, double *b, hipStream_t st);
 // GEMM operand matrix (n atoms, ncols logical columns) to FP64 (hi + lo for
 // BF16); atom i's row is row[i] (NULL: i)
 template <typename T>

@@ -304,15 +304,18 @@ __global__ void __launch_bounds__(256) k_emb_fwd(int natoms, EnvArgs A, const re
         T1[k] *= sigma;
         Tl[k * kM + lane] = T0[k];
         Tl[k * kM + lane + 64] = T1[k];
-        T_out[(long)i * 4 * kM + k * kM + lane] = T0[k];
-        T_out[(long)i * 4 * kM + k * kM + lane + 64] = T1[k];
     }
+    // T out by column: (T_0c, T_1c, T_2c, T_3c) for c < M, one vector store per column
+    V4<real> *T4 = reinterpret_cast<V4<real> *>(T_out) + (long)i * kM;
+    T4[lane] = V4<real>{T0[0], T0[1], T0[2], T0[3]};
+    T4[lane + 64] = V4<real>{T1[0], T1[1], T1[2], T1[3]};
     wave_sync();
     // D[a][b] = sum_k T[k][a] T[k][b], a < M<: lane owns b = lane, lane + 64;
-    // the row of the atom in the fitting net's operand (grouped by type)
+    // the row of the atom in the fitting net's operand (grouped by type).
+    // No D_out: the first fitting layer forms D from T itself.
     const long drow = fit_row(A, i);
 #pragma unroll 4
-    for (int a = 0; a < kMlt; a++) {
+    for (int a = 0; a < (D_out ? kMlt : 0); a++) {
         real d0 = 0, d1 = 0;
 #pragma unroll
         for (int k = 0; k < 4; k++) {
@@ -365,25 +368,30 @@ __global__ void __launch_bounds__(256) k_emb_bwd(int natoms, EnvArgs A, const re
     {
         constexpr int APG = kMlt / NG;
         int g = lane / GL, l = lane % GL;
-        const real *Ti = T + (long)i * 4 * kM;
+        const V4<real> *Ti = reinterpret_cast<const V4<real> *>(T) + (long)i * kM;   // T by column
         const real *dDi = dD + fit_row(A, i) * kDdim;
         real dt[4][CPL], tc[4][CPL];
 #pragma unroll
-        for (int c = 0; c < CPL; c++)
+        for (int c = 0; c < CPL; c++) {
+            V4<real> t = Ti[l + GL * c];
+            tc[0][c] = t.x;
+            tc[1][c] = t.y;
+            tc[2][c] = t.z;
+            tc[3][c] = t.w;
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-                tc[k][c] = Ti[k * kM + l + GL * c];
-                dt[k][c] = 0;
-            }
+            for (int k = 0; k < 4; k++) dt[k][c] = 0;
+        }
 #pragma unroll
         for (int qa = 0; qa < APG; qa++) {
             int a0 = g * APG + qa;
             real ta[4], s2[4];
+            V4<real> t = Ti[a0];
+            ta[0] = t.x;
+            ta[1] = t.y;
+            ta[2] = t.z;
+            ta[3] = t.w;
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-                ta[k] = Ti[k * kM + a0];
-                s2[k] = 0;
-            }
+            for (int k = 0; k < 4; k++) s2[k] = 0;
 #pragma unroll
             for (int c = 0; c < CPL; c++) {
                 real v = dDi[a0 * kM + l + GL * c];

@@ -422,6 +422,16 @@ __global__ void k_to_double<double>(long n, const double *__restrict__ a, double
 }
 
 template <typename T>
+__global__ void k_tcol_to_double(long n, const T *__restrict__ a, double *__restrict__ b)
+{
+    long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;   // output element (i, k, c)
+    if (idx >= n) return;
+    long i = idx / (4 * kM);
+    int k = (int)(idx / kM % 4), c = (int)(idx % kM);
+    b[idx] = (double)a[(i * kM + c) * 4 + k];
+}
+
+template <typename T>
 __global__ void k_op_to_double(long n, int ncols, const T *__restrict__ a, const int *__restrict__ rowmap,
                                double *__restrict__ b)
 {
@@ -514,6 +524,15 @@ void launch_to_double(long n, const T *a, double *b, hipStream_t st)
 template void launch_to_double<double>(long, const double *, double *, hipStream_t);
 template void launch_to_double<float>(long, const float *, double *, hipStream_t);
 template void launch_to_double<__bf16>(long, const __bf16 *, double *, hipStream_t);
+
+template <typename T>
+void launch_tcol_to_double(int n, const T *a, double *b, hipStream_t st)
+{
+    long tot = (long)n * 4 * kM;
+    if (tot > 0) hipLaunchKernelGGL((k_tcol_to_double<T>), dim3(div_up(tot, 256)), dim3(256), 0, st, tot, a, b);
+}
+template void launch_tcol_to_double<double>(int, const double *, double *, hipStream_t);
+template void launch_tcol_to_double<float>(int, const float *, double *, hipStream_t);
 
 template <typename T>
 void launch_op_to_double(int n, int ncols, const T *a, const int *row, double *b, hipStream_t st)

@@ -79,6 +79,12 @@ __device__ inline void epi4(const Epi &e, const float *bias, const float *resv, 
     }
 }
 
+// Four elements of T (one column) as a native vector.
+template <typename T> struct TV4;
+template <> struct TV4<double> { using type = d4v; };
+template <> struct TV4<float> { using type = f4v; };
+template <> struct TV4<__bf16> { using type = f4v; };
+
 // N 16-byte chunks of a stage held by one thread: chunk r of thread tid is
 // row (tid + 256 r) / 8, byte column 16 ((tid + 256 r) mod 8) of the tile.
 template <int N>
@@ -111,7 +117,16 @@ struct Stage<0> {
 // grid is 1-D: tile t goes to block (t mod 8) * (T / 8) + t / 8 order, i.e.
 // consecutive tiles (the column tiles of one row tile first) land on the same
 // XCD, whose L2 then serves the shared A rows.
-template <typename TA, typename TR, int EPI, int TM, int TN>
+//
+// DT (first fitting layer, FP32 / FP64): A is the descriptor D = T<^T T
+// (Eq. 2) of each row's atom, formed from T while the stage is staged
+// instead of read from a stored D.  K then runs in the order
+// k' = b M< + a (a < M<, b < M), which the weights' copy V1tp follows, so a
+// stage covers whole columns b of D: a thread keeps the T<[k][a] of its
+// chunk's a in registers for the whole loop and loads the four T[k][b] of
+// each stage, one vector (T is stored by column: (T_0b, .., T_3b)).  Each element is summed as the embedding kernel sums D
+// (k = 0..3, fused multiply-adds from zero), so both forms are bit-equal.
+template <typename TA, typename TR, int EPI, int TM, int TN, bool DT = false>
 __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const TA *__restrict__ A,
                                                  const TA *__restrict__ Bt, Epi e)
 {
@@ -140,7 +155,7 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const TA *
     for (int g = 1; g < e.ntr; g++) ty += row0 >= e.trow[g] ? 1 : 0;
     Bt += ty * e.bstride;
 
-    const char *Ag = reinterpret_cast<const char *>(A) + (long)row0 * K * sizeof(TA);
+    const char *Ag = DT ? nullptr : reinterpret_cast<const char *>(A) + (long)row0 * K * sizeof(TA);
     const char *Bg = reinterpret_cast<const char *>(Bt) + (long)col0 * K * sizeof(TA);
     long ld = (long)K * sizeof(TA);
     // register staging of the next stage (all indices compile-time)
@@ -153,15 +168,74 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const TA *
         for (int b = 0; b < TN; b++) acc[a][b] = accv{0, 0, 0, 0};
 
     int KT = K / BK;
-    ra.load(Ag, ld, 0, tid);
+    // DT: chunk rr of this thread is row (tid / 8) + 32 rr of the tile and
+    // elements VEC (tid mod 8) .. + VEC of the stage, i.e. a = that mod M<
+    // and one b per stage; rows without an atom (padding) get D = 0
+    constexpr int VEC = 16 / (int)sizeof(TA);
+    constexpr int NL = DT ? LA : 1;
+    using TV = typename TV4<TA>::type;
+    const TV *Trow[NL];
+    TA tl[NL][4][VEC], tb[NL][4];
+    const int pa = tid & 7;
+    if constexpr (DT) {
+        const TV *Tg = reinterpret_cast<const TV *>(e.dt_T);
+#pragma unroll
+        for (int rr = 0; rr < LA; rr++) {
+            int gm = row0 + (tid >> 3) + 32 * rr;
+            int atom = e.dt_ratom ? e.dt_ratom[gm] : (gm < e.dt_nlive ? gm : -1);
+            Trow[rr] = Tg + (long)(atom >= 0 ? atom : 0) * kM;
+#pragma unroll
+            for (int v = 0; v < VEC; v++) {
+                TV t = Trow[rr][(pa * VEC) % kMlt + v];
+#pragma unroll
+                for (int k = 0; k < 4; k++) tl[rr][k][v] = atom >= 0 ? t[k] : (TA)0;
+            }
+        }
+    }
+    // A of stage kt into registers, and from there into an LDS buffer
+    auto a_load = [&](int kt) {
+        if constexpr (DT) {
+            const int b = (kt * BK + pa * VEC) / kMlt;
+#pragma unroll
+            for (int rr = 0; rr < LA; rr++) {
+                TV t = Trow[rr][b];
+#pragma unroll
+                for (int k = 0; k < 4; k++) tb[rr][k] = t[k];
+            }
+        } else {
+            ra.load(Ag, ld, kt, tid);
+        }
+    };
+    auto a_store = [&](char *as) {
+        if constexpr (DT) {
+#pragma unroll
+            for (int rr = 0; rr < LA; rr++) {
+                TA d[VEC];
+#pragma unroll
+                for (int v = 0; v < VEC; v++) {
+                    TA x = (TA)0;
+#pragma unroll
+                    for (int k = 0; k < 4; k++) x = fma(tl[rr][k][v], tb[rr][k], x);
+                    d[v] = x;
+                }
+                u4v w;
+                __builtin_memcpy(&w, d, 16);
+                int c = tid + 256 * rr;
+                *reinterpret_cast<u4v *>(as + (c >> 3) * ROWB + (c & 7) * 16) = w;
+            }
+        } else {
+            ra.store(as, tid);
+        }
+    };
+    a_load(0);
     rb.load(Bg, ld, 0, tid);
-    ra.store(As[0], tid);
+    a_store(As[0]);
     rb.store(Bs[0], tid);
     __syncthreads();
     for (int kt = 0; kt < KT; kt++) {
         int buf = kt & 1;
         if (kt + 1 < KT) {
-            ra.load(Ag, ld, kt + 1, tid);
+            a_load(kt + 1);
             rb.load(Bg, ld, kt + 1, tid);
         }
 #pragma unroll
@@ -180,7 +254,7 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const TA *
                 for (int b = 0; b < TN; b++) mfma_any<TA>(fa[a], fb[b], acc[a][b]);
         }
         if (kt + 1 < KT) {
-            ra.store(As[buf ^ 1], tid);
+            a_store(As[buf ^ 1]);
             rb.store(Bs[buf ^ 1], tid);
         }
         __syncthreads();
@@ -307,6 +381,19 @@ void launch_gemm(int epi, int M, int N, int K, const TA *A, const TA *Bt, const 
     else if (N % 128 == 0 && M % 128 == 0) launch_gemm_t<TA, TR, 4, 4>(epi, M, N, K, A, Bt, e, st);
     else launch_gemm_t<TA, TR, 2, 2>(epi, M, N, K, A, Bt, e, st);
 }
+template <typename TA, typename TR>
+void launch_gemm_dt(int M, int N, const TA *Bt, const Epi &e, hipStream_t st)
+{
+    // FP64: 64 x 64 tiles (as launch_gemm takes for the first layer); FP32: 128 x 128
+    constexpr int TM = std::is_same<TA, double>::value ? 2 : 4, TN = TM;
+    constexpr int BM = 32 * TM, BN = 32 * TN;
+    int ntiles = (N / BN) * div_up(M, BM);
+    hipLaunchKernelGGL((k_gemm_nt<TA, TR, EPI_T1, TM, TN, true>), dim3(8 * div_up(ntiles, 8)), dim3(256), 0, st, M, N,
+                       kDdim, (const TA *)nullptr, Bt, e);
+}
+template void launch_gemm_dt<double, double>(int, int, const double *, const Epi &, hipStream_t);
+template void launch_gemm_dt<float, float>(int, int, const float *, const Epi &, hipStream_t);
+
 template void launch_gemm<double, double>(int, int, int, int, const double *, const double *, const Epi &, hipStream_t);
 template void launch_gemm<float, float>(int, int, int, int, const float *, const float *, const Epi &, hipStream_t);
 template void launch_gemm<__bf16, float>(int, int, int, int, const __bf16 *, const __bf16 *, const Epi &, hipStream_t);
