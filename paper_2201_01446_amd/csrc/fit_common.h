@@ -4,6 +4,7 @@
 #pragma once
 
 #include "dp_internal.h"
+#include "tanh64.h"
 
 #include <type_traits>
 
@@ -65,7 +66,7 @@ template <> __device__ inline double tod<double>(double v) { return v; }
 template <> __device__ inline __bf16 tod<__bf16>(double v) { return (__bf16)(float)v; }
 
 __device__ inline float tanh_r(float v) { return tanhf(v); }
-__device__ inline double tanh_r(double v) { return tanh(v); }
+__device__ inline double tanh_r(double v) { return tanh_f64(v); }
 
 // tanh of an epilogue: native, or from the second-order table on [0, 8)
 // (odd extension, 1 beyond 8), read in the epilogue's precision.
@@ -83,7 +84,7 @@ __device__ inline float tanh_e(float x, const float *tab)
 }
 __device__ inline double tanh_e(double x, const double *tab)
 {
-    if (!tab) return tanh(x);
+    if (!tab) return tanh_f64(x);
     double ax = fabs(x);
     if (ax >= 8.0) return copysign(1.0, x);
     int k = (int)(ax * (kTanhN / 8.0));

@@ -19,6 +19,7 @@
 #include "dp_internal.h"
 #include "emb_common.h"
 #include "env.h"
+#include "tanh64.h"
 
 #include <type_traits>
 
@@ -29,7 +30,7 @@ namespace {
 template <typename real>
 __device__ inline real tanh_p(real v);
 template <> __device__ inline float tanh_p<float>(float v) { return tanhf(v); }
-template <> __device__ inline double tanh_p<double>(double v) { return tanh(v); }
+template <> __device__ inline double tanh_p<double>(double v) { return tanh_f64(v); }
 
 template <typename T> __device__ inline T cvd(double v);
 template <> __device__ inline double cvd<double>(double v) { return v; }
