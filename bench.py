@@ -140,17 +140,20 @@ def run_nve(P, model, x0, v0, box, steps, warmup, precision, mode=0, keep=False,
     return out
 
 
-def kernel_work(N, sum_nei, sum_seg, rs):
+def kernel_work(N, sum_nei, sum_seg, rs, d_in_emb):
     """Algorithmic work per launch of each kernel (FMA = 2 FLOP) and its
     bound: the fitting GEMMs count the model's 240 columns (not the padded
     256) and one pass of K (not the BF16 hi/lo split's three); the embedding
     kernels count the interval-moment form they execute: forward 24 moments
-    per neighbor, 24 per (segment, column), D 16 x 128 x 4; backward dE/dT
-    2 x 16 x 128 x 4, 24 per (segment, column), 40 per neighbor."""
+    per neighbor, 24 per (segment, column), and D 16 x 128 x 4 where it forms
+    D (d_in_emb: the mixed mode; in FP32 and FP64 the first fitting layer
+    forms D from T, VALU work beside its MFMA product that is not counted);
+    backward dE/dT 2 x 16 x 128 x 4, 24 per (segment, column), 40 per
+    neighbor."""
     fit_in = N * 2.0 * 240 * 2048          # 2048 -> 240 (and its transpose)
     fit_hid = N * 2.0 * 240 * 240          # 240 -> 240
     return {
-        "emb_fwd": (2.0 * (24 * sum_nei + 24 * 128 * sum_seg + 8192 * N), "alu"),
+        "emb_fwd": (2.0 * (24 * sum_nei + 24 * 128 * sum_seg + (8192 * N if d_in_emb else 0)), "alu"),
         "emb_bwd": (2.0 * (16384 * N + 24 * 128 * sum_seg + 40 * sum_nei), "alu"),
         "fit_fwd1": (fit_in, "mfma"), "fit_bwd1": (fit_in, "mfma"),
         "fit_fwd2": (fit_hid, "mfma"), "fit_fwd3": (fit_hid, "mfma"),
@@ -263,7 +266,7 @@ def main():
     summary = {}
     for name, prec, dt_alu, dt_mfma, rs in legs:
         r = runs[name]
-        roof, per = roofline(r, K, kernel_work(N, sum_nei, sum_seg, rs), dt_alu, dt_mfma,
+        roof, per = roofline(r, K, kernel_work(N, sum_nei, sum_seg, rs, name == "mixed_bf16"), dt_alu, dt_mfma,
                              {"fp64": "f64", "fp32": "f32", "mixed_bf16": "bf16"}[name])
         th = r["thermo"]
         etot = th[:, 0] + th[:, 1]
