@@ -134,6 +134,12 @@ __device__ inline double group_sum(double v)
     return v;
 }
 
+// One DPP move of a float or a double.
+template <int CTRL>
+__device__ inline float dpp_any(float v) { return dpp_f<CTRL>(v); }
+template <int CTRL>
+__device__ inline double dpp_any(double v) { return dpp_d<CTRL>(v); }
+
 // Representatives of the ns segments of a round starting at s0: lane u < ns
 // returns the first segment v <= u of the round with the same table interval
 // (the clamp bit aside); other lanes return themselves.
@@ -333,6 +339,77 @@ __global__ void __launch_bounds__(256) k_emb_fwd(int natoms, EnvArgs A, const re
 }
 
 // ------------------------------------------------------------- backward
+// B[k][e] = sum_c dT[k][c] a[theta][c][e] for the ns segments of a round
+// starting at s0, 2^lg lanes per segment (lg = 2 in a full round; the last
+// round's segments get more): segment s0 + (lane >> lg), its lanes taking
+// columns c = 2^lg m + (lane mod 2^lg), then summed over the group, whose
+// first lane stores B at Bs[(lane >> lg) * 24].  FULL: lg = 2 known at
+// compile time.
+template <typename real, bool FULL>
+__device__ inline void round_B(const NbrLDS<real> &L, const int *seg, int s0, int ns, int lg,
+                               const real *__restrict__ tab, const V4<real> *dTl, real *Bs, int lane)
+{
+    if (FULL) lg = 2;
+    const int G = 1 << lg, q = lane >> lg, ql = lane & (G - 1);
+    real B[4][6];
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+#pragma unroll
+        for (int e = 0; e < 6; e++) B[k][e] = 0;
+    if (q < ns) {
+        int th = L.th[seg[s0 + q]] & ~kOobBit;
+        // full rounds: in FP64 every coefficient load of the segment in flight
+        // at once, in FP32 four (measured fastest for each); wider groups: two
+        constexpr int kLoadsInFlight = !FULL ? 2 : sizeof(real) == 8 ? kM / 4 : 4;
+#pragma unroll kLoadsInFlight
+        for (int m = 0; m < (kM >> lg); m++) {
+            int c = (m << lg) + ql;
+            V4<real> d = dTl[c];
+            real a[6];
+            coef_col(tab, th, c, a);
+#pragma unroll
+            for (int e = 0; e < 6; e++) {
+                B[0][e] = fma(d.x, a[e], B[0][e]);
+                B[1][e] = fma(d.y, a[e], B[1][e]);
+                B[2][e] = fma(d.z, a[e], B[2][e]);
+                B[3][e] = fma(d.w, a[e], B[3][e]);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+#pragma unroll
+        for (int e = 0; e < 6; e++) B[k][e] = quad_sum(B[k][e]);
+    if (!FULL) {
+        // the rest of the group (wave-uniform steps): within 8 and 16 lanes by
+        // DPP mirrors, then across rows
+        if (lg >= 3) {
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+#pragma unroll
+                for (int e = 0; e < 6; e++) B[k][e] += dpp_any<0x141>(B[k][e]);
+        }
+        if (lg >= 4) {
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+#pragma unroll
+                for (int e = 0; e < 6; e++) B[k][e] += dpp_any<0x140>(B[k][e]);
+        }
+        for (int off = 16; off < G; off <<= 1) {
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+#pragma unroll
+                for (int e = 0; e < 6; e++) B[k][e] += __shfl_xor(B[k][e], off);
+        }
+    }
+    if (q < ns && ql == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+#pragma unroll
+            for (int e = 0; e < 6; e++) Bs[q * 24 + k * 6 + e] = B[k][e];
+    }
+}
+
 // CPL: columns per lane in the dE/dT prologue (lanes in NG groups of GL).
 template <typename real, int CPL>
 __global__ void __launch_bounds__(256) k_emb_bwd(int natoms, EnvArgs A, const real *__restrict__ tab,
@@ -421,50 +498,17 @@ __global__ void __launch_bounds__(256) k_emb_bwd(int natoms, EnvArgs A, const re
     }
     int nseg = find_segments(L, nn, lane, seg);   // its wave barrier also publishes dT
 
-    int q = lane >> 2, ql = lane & 3;
     real Fi0 = 0, Fi1 = 0, Fi2 = 0;
     real W[9];
 #pragma unroll
     for (int r = 0; r < 9; r++) W[r] = 0;
     for (int s0 = 0; s0 < nseg; s0 += kSegRound) {
         int ns = min(kSegRound, nseg - s0);
-        // B[k][e] = sum_c dT[k][c] a[theta][c][e] of segment s0 + q; the
-        // quad's lanes take columns c = 4 m + ql
-        real B[4][6];
-#pragma unroll
-        for (int k = 0; k < 4; k++)
-#pragma unroll
-            for (int e = 0; e < 6; e++) B[k][e] = 0;
-        if (q < ns) {
-            int th = L.th[seg[s0 + q]] & ~kOobBit;
-            // FP64: every coefficient load of the segment in flight at once;
-            // FP32: four (measured fastest for each)
-            constexpr int kLoadsInFlight = sizeof(real) == 8 ? kM / 4 : 4;
-#pragma unroll kLoadsInFlight
-            for (int m = 0; m < kM / 4; m++) {
-                int c = 4 * m + ql;
-                V4<real> d = dTl[c];
-                real a[6];
-                coef_col(tab, th, c, a);
-#pragma unroll
-                for (int e = 0; e < 6; e++) {
-                    B[0][e] = fma(d.x, a[e], B[0][e]);
-                    B[1][e] = fma(d.y, a[e], B[1][e]);
-                    B[2][e] = fma(d.z, a[e], B[2][e]);
-                    B[3][e] = fma(d.w, a[e], B[3][e]);
-                }
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < 4; k++)
-#pragma unroll
-            for (int e = 0; e < 6; e++) B[k][e] = quad_sum(B[k][e]);
-        if (q < ns && ql == 0) {
-#pragma unroll
-            for (int k = 0; k < 4; k++)
-#pragma unroll
-                for (int e = 0; e < 6; e++) Bs[q * 24 + k * 6 + e] = B[k][e];
-        }
+        // B of the round's segments: four lanes per segment in a full round;
+        // a round of at most 8, 4, 2 or 1 segments (the last one) gives each
+        // 8, 16, 32 or 64 lanes, so its lanes still share the columns
+        if (ns > 8) round_B<real, true>(L, seg, s0, ns, 2, tab, dTl, Bs, lane);
+        else round_B<real, false>(L, seg, s0, ns, ns > 4 ? 3 : ns > 2 ? 4 : ns > 1 ? 5 : 6, tab, dTl, Bs, lane);
         wave_sync();
         // the neighbors of these segments, one per lane: dE/dR_j and dE/ds_j
         // from B, then the chain rule through Eq. 1 and the scatter
