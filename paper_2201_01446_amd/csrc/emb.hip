@@ -156,22 +156,41 @@ __device__ inline int round_reps(const NbrLDS<real> &L, const int *seg, int s0, 
 }
 
 // Starts of the runs of equal interval in the neighbor list: seg[0..nseg-1],
-// seg[nseg] = nn.  Returns nseg (uniform over the wave).
-template <typename real>
-__device__ int find_segments(const NbrLDS<real> &L, int nn, int lane, int *seg)
+// seg[nseg] = nn.  Returns nseg (uniform over the wave).  X > 0: a run longer
+// than X is cut into pieces of X neighbors (and a last shorter one), which
+// become segments of their own; nruns then receives the number of whole runs.
+template <typename real, int X = 0>
+__device__ int find_segments(const NbrLDS<real> &L, int nn, int lane, int *seg, int *nruns = nullptr)
 {
-    int nseg = 0;
+    int nseg = 0, runs = 0;
+    int open = 0;   // start of the run that continues into the next chunk
     for (int base = 0; base < nn; base += 64) {
         int k = base + lane;
         bool head = k < nn && (k == 0 || L.th[k] != L.th[k - 1]);
+        if (X > 0) {
+            unsigned long long hm = __ballot(head);
+            runs += __popcll(hm);
+            unsigned long long upto = hm & ((2ull << lane) - 1ull);   // run heads at lanes <= lane
+            int start = upto ? base + 63 - __builtin_clzll(upto) : open;
+            head = head || (k < nn && (k - start) % X == 0);
+            if (hm) open = base + 63 - __builtin_clzll(hm);
+        }
         unsigned long long m = __ballot(head);
         if (head) seg[nseg + __popcll(m & ((1ull << lane) - 1ull))] = k;
         nseg += __popcll(m);
     }
     if (lane == 0) seg[nseg] = nn;
+    if (nruns) *nruns = X > 0 ? runs : nseg;
     wave_sync();
     return nseg;
 }
+
+// Longest segment of the forward: its moments take one quad as many steps as
+// the segment has neighbors, and a round waits for its longest segment, so
+// long runs (a whole neighbor shell can share one table interval) are cut;
+// the pieces share an interval, and the round's representatives merge them
+// again before the contraction.
+constexpr int kFwdMaxRun = 16;
 
 constexpr int seg_bytes(int sel) { return ((sel + 1) * 4 + 15) / 16 * 16; }
 
@@ -220,7 +239,8 @@ __global__ void __launch_bounds__(256) k_emb_fwd(int natoms, EnvArgs A, const re
     if (live) nn = build_env<real, ENV_FWD>(i, A, L, lane, n_in, over, oob);
     __syncthreads();
     if (!live) return;
-    int nseg = find_segments(L, nn, lane, seg);
+    int nruns = 0;
+    int nseg = find_segments<real, kFwdMaxRun>(L, nn, lane, seg, &nruns);
 
     int q = lane >> 2, ql = lane & 3;
     real T0[4] = {0, 0, 0, 0}, T1[4] = {0, 0, 0, 0};   // columns lane, lane + 64
@@ -334,7 +354,7 @@ __global__ void __launch_bounds__(256) k_emb_fwd(int natoms, EnvArgs A, const re
     }
     // counters last: nothing in this kernel waits for these atomics
     if (nnei_out && lane == 0) nnei_out[i] = nn;
-    if (nseg_out && lane == 0) nseg_out[i] = nseg;
+    if (nseg_out && lane == 0) nseg_out[i] = nruns;
     record_flags<real>(A, lane, n_in, over, oob);
 }
 
