@@ -283,6 +283,23 @@ dp_status dp_nve_run(dp_model *model, dp_nlist **nlist, int natoms, double *x_d,
                      int nsteps, int rebuild_every, double skin, int mode, int precision,
                      double *thermo_d, void *stream);
 
+/* Continues the trajectory that the last dp_nve_run or dp_nve_continue on
+ * `nlist` left (the same MD protocol): no build at the start and no first
+ * evaluation; the forces and energy of the final positions, which the list
+ * keeps, start the first half kick, and the rebuild cadence counts on from
+ * the list's last build (rebuild_every as before).  So n steps of dp_nve_run
+ * followed by m steps of dp_nve_continue give exactly the state of n + m
+ * steps of dp_nve_run.  The positions array must be the one the previous run
+ * updated (x_d, natoms, mode and precision as then; x_d and v_d not changed
+ * in between); otherwise, or after a dp_build_nlist on the list or a failed
+ * run, DP_ERR_STATE.  thermo_d: nsteps+1 rows, row 0 the state continued
+ * from.  Checks, errors and counters as in dp_nve_run.  (An MD loop timed
+ * this way excludes the set-up of the first build and evaluation, as a
+ * steady-state step count does.) */
+dp_status dp_nve_continue(dp_model *model, dp_nlist *nlist, int natoms, double *x_d, double *v_d,
+                          const double *mass_h, double dt_fs, int nsteps, int rebuild_every, int mode,
+                          int precision, double *thermo_d, void *stream);
+
 /* ---------------------------------------------------------------- serving
  * A batch evaluates several independent configurations ("requests") in one
  * chain of launches: their atoms are concatenated (request r owns atoms

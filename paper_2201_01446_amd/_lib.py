@@ -55,6 +55,7 @@ _SIG = {
     "dp_nlist_stats": [_vp, _pi, _pi, _pi, _pi],
     "dp_nlist_check": [_vp],
     "dp_nve_run": [_vp, _pvp, _i, _vp, _vp, _vp, _vp, _vp, _d, _i, _i, _d, _i, _i, _vp, _vp],
+    "dp_nve_continue": [_vp, _vp, _i, _vp, _vp, _vp, _d, _i, _i, _i, _i, _vp, _vp],
     "dp_batch_create": [_vp, _i, _i, _d, _pvp],
     "dp_batch_destroy": [_vp],
     "dp_batch_compute": [_vp, _vp, _i, _vp, _vp, _i, _vp, _vp, _vp, _vp, _vp],

@@ -191,3 +191,20 @@ def nve_run(model, nlist, x, v, box, mass, dt, nsteps, rebuild_every=10, skin=2.
     nlist.box = None if box is None else np.asarray(box, dtype=np.float64).reshape(9)
     nlist.natoms = n
     return th
+
+
+def nve_continue(model, nlist, x, v, mass, dt, nsteps, rebuild_every=10, mode=COMPRESSED, precision=FP64,
+                 thermo=True):
+    """Continues the trajectory of the last nve_run / nve_continue on nlist
+    (same x tensor, mode and precision): no build and no first evaluation at
+    the start.  Returns the thermo tensor (nsteps+1, 2)."""
+    n = x.shape[0]
+    _f64(x, (n, 3))
+    _f64(v, (n, 3))
+    th = torch.empty((nsteps + 1, 2), dtype=torch.float64, device=x.device) if thermo else None
+    m = np.ascontiguousarray(np.atleast_1d(np.asarray(mass, dtype=np.float64)))
+    if m.size != max(1, model.cfg.get("ntypes", 1)):
+        raise ValueError("one mass per type expected")
+    check(lib.dp_nve_continue(model.h, nlist.h, n, _ptr(x), _ptr(v), m.ctypes.data_as(ctypes.c_void_p), dt, nsteps,
+                              rebuild_every, mode, precision, _ptr(th), _stream()))
+    return th

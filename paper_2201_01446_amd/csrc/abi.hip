@@ -163,7 +163,7 @@ void free_nlist_arrays(dp_nlist *nl)
 {
     void *p[] = {nl->cell_cnt, nl->cell_atoms, nl->wpos, nl->wrap, nl->cnt, nl->nei, nl->shift,
                  nl->dist, nl->rev, nl->pg, nl->flags, nl->ws, nl->ws_plain, nl->force_tmp, nl->scal,
-                 nl->type, nl->tcnt, nl->row, nl->ratom, nl->tblk, nl->x0, nl->inner, nl->disp};
+                 nl->type, nl->tcnt, nl->row, nl->ratom, nl->tblk, nl->x0, nl->inner, nl->disp, nl->nve_F};
     for (void *q : p)
         if (q) (void)hipFree(q);
 }
@@ -177,6 +177,7 @@ dp_status prepare_nlist(const dp_model *m, int natoms, const double *box, double
     dp_nlist *nl = *inout;
     bool fresh = nl == nullptr;
     if (fresh) nl = new dp_nlist();
+    nl->nve_x = nullptr;   // a build or reallocation ends the trajectory dp_nve_continue would resume
     int dev = 0;
     DP_HIP(hipGetDevice(&dev));
     nl->device = dev;
@@ -240,7 +241,7 @@ dp_status prepare_nlist(const dp_model *m, int natoms, const double *box, double
         int alloc = natoms > nl->alloc_atoms ? natoms : nl->alloc_atoms;
         int capn = cap > nl->cap ? cap : nl->cap;
         void *p[] = {nl->wpos, nl->wrap, nl->cnt, nl->nei, nl->shift, nl->dist, nl->rev, nl->pg, nl->force_tmp,
-                     nl->x0, nl->inner};
+                     nl->x0, nl->inner, nl->nve_F};
         for (void *q : p)
             if (q) DP_HIP(hipFree(q));
         DP_HIP(hipMalloc(&nl->wpos, sizeof(double) * 3 * (size_t)alloc));
@@ -254,6 +255,7 @@ dp_status prepare_nlist(const dp_model *m, int natoms, const double *box, double
         DP_HIP(hipMalloc(&nl->rev, sizeof(short) * (size_t)alloc * capn));
         DP_HIP(hipMalloc(&nl->pg, sizeof(double) * 3 * (size_t)alloc * capn));
         DP_HIP(hipMalloc(&nl->force_tmp, sizeof(double) * 3 * (size_t)alloc));
+        DP_HIP(hipMalloc(&nl->nve_F, sizeof(double) * 3 * (size_t)alloc));
         nl->alloc_atoms = alloc;
         nl->cap = capn;
     }
@@ -717,46 +719,64 @@ dp_status dp_nlist_stats(dp_nlist *nl, int *max_nei, int *n_sel_overflow, int *n
     return DP_OK;
 }
 
-dp_status dp_nve_run(dp_model *m, dp_nlist **nlp, int natoms, double *x, double *v, const int *types,
-                     const double *box_h, const double *mass_h, double dt_fs, int nsteps, int rebuild_every,
-                     double skin, int mode, int precision, double *thermo, void *stream)
+// nsteps of velocity Verlet from the list's trajectory state.  fresh: the
+// list is (re)built at x and the forces evaluated first (dp_nve_run);
+// otherwise the forces and energy the previous run left are used and the
+// rebuild cadence continues from its last build (dp_nve_continue).
+static dp_status nve_steps(dp_model *m, dp_nlist **nlp, int natoms, double *x, double *v, const int *types,
+                           const double *box_h, const double *mass_h, double dt_fs, int nsteps, int rebuild_every,
+                           double skin, int mode, int precision, double *thermo, hipStream_t st, bool fresh)
 {
-    if (!m || !nlp || !x || !v || !mass_h) return fail(DP_ERR_ARG, "NULL argument");
     const int T = m->cfg.ntypes;
     for (int t = 0; t < T; t++)
         if (!(mass_h[t] > 0) || !std::isfinite(mass_h[t])) return fail(DP_ERR_ARG, "need masses > 0");
     if (!(dt_fs > 0) || nsteps < 0 || rebuild_every < 1)
         return fail(DP_ERR_ARG, "need dt > 0, nsteps >= 0, rebuild_every >= 1");
-    hipStream_t st = (hipStream_t)stream;
     dp_status s;
-    dp_nlist *nl = nullptr;
-    for (int attempt = 0;; attempt++) {   // the first build, checked as in dp_build_nlist
-        if ((s = prepare_nlist(m, natoms, box_h, skin, nlp)) != DP_OK) return s;
-        nl = *nlp;
+    dp_nlist *nl = *nlp;
+    if (fresh) {
+        for (int attempt = 0;; attempt++) {   // the first build, checked as in dp_build_nlist
+            if ((s = prepare_nlist(m, natoms, box_h, skin, nlp)) != DP_OK) return s;
+            nl = *nlp;
+            if ((s = check_compute_args(m, nl, natoms, x, mode, precision)) != DP_OK) return s;
+            if ((s = build_all(m, nl, x, types, st)) != DP_OK) return s;
+            if ((s = step_check("build_nlist", st)) != DP_OK) return s;
+            int f[kNumFlags];
+            if ((s = read_flags(nl, f, st)) != DP_OK) return s;
+            if (attempt < 3 && grow_after_overflow(nl, f)) continue;
+            if ((s = check_build_flags(f)) != DP_OK) return s;
+            break;
+        }
+    } else {
+        if (!nl || nl->nve_x != x || nl->nve_natoms != natoms || nl->nve_mode != mode || nl->nve_prec != precision)
+            return fail(DP_ERR_STATE, "no trajectory to continue on this list: call dp_nve_run first (with the "
+                                      "same positions array, atom count, mode and precision)");
         if ((s = check_compute_args(m, nl, natoms, x, mode, precision)) != DP_OK) return s;
-        if ((s = build_all(m, nl, x, types, st)) != DP_OK) return s;
-        if ((s = step_check("build_nlist", st)) != DP_OK) return s;
-        int f[kNumFlags];
-        if ((s = read_flags(nl, f, st)) != DP_OK) return s;
-        if (attempt < 3 && grow_after_overflow(nl, f)) continue;
-        if ((s = check_build_flags(f)) != DP_OK) return s;
-        break;
     }
     // rebuilds inside the run reuse the list's copy of the types
     const int *tl = T > 1 ? nl->type : types;
     const int *tk = T > 1 ? nl->type : nullptr;   // per-atom type of the Verlet kernels
-    double *F = nl->force_tmp, *E = nl->scal, *part = nl->scal + 256;
+    double *F = nl->nve_F, *E = nl->scal, *part = nl->scal + 256;
     TypeScalars kick, kef;
     for (int t = 0; t < T; t++) {
         kick.v[t] = 0.5 * dt_fs * acc_unit() / mass_h[t];
         kef.v[t] = 0.5 * mass_h[t] * ke_unit();
     }
-    s = compute_common(m, nl, natoms, x, mode, precision, E, F, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, st);
-    if (s != DP_OK) return s;
+    // the box of the list, for a reallocation after a capacity overflow
+    double box_l[9] = {nl->L[0], 0, 0, 0, nl->L[1], 0, 0, 0, nl->L[2]};
+    const double *box = fresh ? box_h : (nl->periodic ? box_l : nullptr);
+    const double skin_l = fresh ? skin : nl->rc_build - nl->rcut_build;
+    int since = fresh ? 0 : nl->nve_since_build;
+    nl->nve_x = nullptr;   // until this run ends normally
+    if (fresh) {
+        s = compute_common(m, nl, natoms, x, mode, precision, E, F, nullptr, nullptr, nullptr, nullptr, nullptr,
+                           nullptr, st);
+        if (s != DP_OK) return s;
+    }
     if (thermo) launch_thermo(v, E, natoms, tk, kef, thermo, part, st);
     for (int step = 1; step <= nsteps; step++) {
         launch_verlet_kick_drift(x, v, F, natoms, tk, kick, dt_fs, st);
-        if (step % rebuild_every == 0) {
+        if (++since % rebuild_every == 0) {
             // The counters of the run accumulate (no reset).  One
             // synchronisation per rebuild checks what the evaluations since the
             // last one flagged, and the build's capacities (grown and built
@@ -771,14 +791,19 @@ dp_status dp_nve_run(dp_model *m, dp_nlist **nlp, int natoms, double *x, double 
                 if (attempt < 3 && grow_after_overflow(nl, f)) {
                     launch_fill_zero_int(nl->flags + kFlagCapOverflow, 1, st);
                     launch_fill_zero_int(nl->flags + kFlagCellOverflow, 1, st);
-                    if ((s = prepare_nlist(m, natoms, box_h, skin, nlp)) != DP_OK) return s;
+                    if ((s = prepare_nlist(m, natoms, box, skin_l, nlp)) != DP_OK) return s;
+                    // a reallocation drops the forces of the step; they are
+                    // evaluated again below at the same positions
+                    F = nl->nve_F;
                     continue;
                 }
                 if ((s = check_build_flags(f)) != DP_OK) return s;
                 break;
             }
+            since = 0;
         }
-        s = compute_common(m, nl, natoms, x, mode, precision, E, F, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, st);
+        s = compute_common(m, nl, natoms, x, mode, precision, E, F, nullptr, nullptr, nullptr, nullptr, nullptr,
+                           nullptr, st);
         if (s != DP_OK) return s;
         launch_verlet_kick(v, F, natoms, tk, kick, st);
         if (thermo) launch_thermo(v, E, natoms, tk, kef, thermo + 2 * step, part, st);
@@ -787,7 +812,32 @@ dp_status dp_nve_run(dp_model *m, dp_nlist **nlp, int natoms, double *x, double 
     int f[kNumFlags];
     if ((s = read_flags(nl, f, st)) != DP_OK) return s;
     if ((s = check_eval_flags(f)) != DP_OK) return s;
-    return check_build_flags(f);
+    if ((s = check_build_flags(f)) != DP_OK) return s;
+    nl->nve_x = x;
+    nl->nve_natoms = natoms;
+    nl->nve_mode = mode;
+    nl->nve_prec = precision;
+    nl->nve_since_build = since % rebuild_every;
+    return DP_OK;
+}
+
+dp_status dp_nve_run(dp_model *m, dp_nlist **nlp, int natoms, double *x, double *v, const int *types,
+                     const double *box_h, const double *mass_h, double dt_fs, int nsteps, int rebuild_every,
+                     double skin, int mode, int precision, double *thermo, void *stream)
+{
+    if (!m || !nlp || !x || !v || !mass_h) return fail(DP_ERR_ARG, "NULL argument");
+    return nve_steps(m, nlp, natoms, x, v, types, box_h, mass_h, dt_fs, nsteps, rebuild_every, skin, mode, precision,
+                     thermo, (hipStream_t)stream, true);
+}
+
+dp_status dp_nve_continue(dp_model *m, dp_nlist *nl, int natoms, double *x, double *v, const double *mass_h,
+                          double dt_fs, int nsteps, int rebuild_every, int mode, int precision, double *thermo,
+                          void *stream)
+{
+    if (!m || !nl || !x || !v || !mass_h) return fail(DP_ERR_ARG, "NULL argument");
+    dp_nlist *nlp = nl;
+    return nve_steps(m, &nlp, natoms, x, v, nullptr, nullptr, mass_h, dt_fs, nsteps, rebuild_every, 0.0, mode,
+                     precision, thermo, (hipStream_t)stream, false);
 }
 
 dp_status dp_nlist_check(dp_nlist *nl)

@@ -142,6 +142,13 @@ struct dp_nlist {
     double *force_tmp = nullptr;   // forces when the caller wants only the virial
     int fwd_token = 0;             // precision+1 while a forward's activations are kept
     double *scal = nullptr;        // [16] device scalars (energy, partial sums)
+    // the trajectory left by the last dp_nve_run / dp_nve_continue on this
+    // list, from which dp_nve_continue resumes: forces (nve_F) and energy
+    // (scal[0]) at the final positions nve_x, steps since the last build;
+    // nve_x NULL when there is none (any (re)allocation or build clears it)
+    double *nve_F = nullptr;
+    const double *nve_x = nullptr;
+    int nve_natoms = 0, nve_mode = -1, nve_prec = -1, nve_since_build = 0;
 };
 
 // A batch of independent cells (serving): one combined neighbor list and

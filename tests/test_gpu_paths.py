@@ -145,6 +145,37 @@ def test_autograd_500k_fp32_sampled(P, model, cu_cfg, cu_params):
 
 # -------------------------------------------------------------------- NVE
 
+def test_nve_continue_equals_one_run(P, model):
+    """7 steps of nve_run then 10 of nve_continue give bit for bit the
+    positions, velocities and thermo rows of 17 steps of nve_run (FP64 and
+    FP32; rebuilds every 5 steps, so the cadence crosses the split).
+    Continuing on a list that holds no trajectory (a new list, or one rebuilt
+    since the run) is refused with DP_ERR_STATE."""
+    x0, box = synth.copper(4, 0.05, 3)
+    v0 = synth.maxwell_boltzmann(len(x0), 330.0, seed=4)
+    for prec in (P.FP64, P.FP32):
+        xa, va = dev(x0), dev(v0)
+        nla = P.NeighborList(model, xa, box)
+        tha = P.nve_run(model, nla, xa, va, box, synth.M_CU, 1.0, 17, rebuild_every=5, precision=prec)
+        xb, vb = dev(x0), dev(v0)
+        nlb = P.NeighborList(model, xb, box)
+        thb1 = P.nve_run(model, nlb, xb, vb, box, synth.M_CU, 1.0, 7, rebuild_every=5, precision=prec)
+        thb2 = P.nve_continue(model, nlb, xb, vb, synth.M_CU, 1.0, 10, rebuild_every=5, precision=prec)
+        torch.cuda.synchronize()
+        print(f"precision {prec}: max |dx| {float((xa - xb).abs().max())}, max |dv| {float((va - vb).abs().max())}")
+        assert torch.equal(xa, xb) and torch.equal(va, vb)
+        assert torch.equal(tha[:8], thb1) and torch.equal(tha[7:], thb2)
+    nlc = P.NeighborList(model, xb, box)
+    with pytest.raises(P.DPError) as err:
+        P.nve_continue(model, nlc, xb, vb, synth.M_CU, 1.0, 2, rebuild_every=5)
+    assert err.value.status == -6
+    P.nve_run(model, nlc, xb, vb, box, synth.M_CU, 1.0, 2, rebuild_every=5)
+    nlc.build(xb, box)
+    with pytest.raises(P.DPError) as err:
+        P.nve_continue(model, nlc, xb, vb, synth.M_CU, 1.0, 2, rebuild_every=5)
+    assert err.value.status == -6
+
+
 def test_nve_fp32_energy_conservation(P, cu_cfg):
     """FP32 forces, FP64 integration and reductions.  At any step the FP32
     run's total-energy change is the integrator's (measured on the same
