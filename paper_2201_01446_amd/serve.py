@@ -17,6 +17,7 @@ than a slot's capacity is rejected on its own (its result says why); the
 others are served.
 """
 import ctypes
+import gc
 import time
 from collections import deque
 
@@ -163,10 +164,25 @@ class Server:
         slot.busy = False
         slot.members = []
 
-    def run(self, requests, arrivals=None):
+    def run(self, requests, arrivals=None, max_batch_atoms=None):
         """requests: list of (coords, box); arrivals: seconds after start at
-        which each request arrives (None: all at once, a closed loop).
-        Returns (results by request, stats)."""
+        which each request arrives (None: all at once, a closed loop);
+        max_batch_atoms: most atoms a slot takes into one batch (None: its
+        capacity; a larger request still goes alone).  Full slots give the most throughput; under a latency
+        target a smaller cap keeps a burst of arrivals from becoming a few
+        large batches that share the GPU and return late.  Returns (results
+        by request, stats).  Python's cyclic garbage collector is paused while
+        the loop runs (a full collection over a large heap stalls admission
+        and completion for tens of ms)."""
+        enabled = gc.isenabled()
+        gc.disable()
+        try:
+            return self._run(requests, arrivals, max_batch_atoms)
+        finally:
+            if enabled:
+                gc.enable()
+
+    def _run(self, requests, arrivals, max_batch_atoms):
         nreq = len(requests)
         arrivals = np.zeros(nreq) if arrivals is None else np.asarray(arrivals, dtype=np.float64)
         order = np.argsort(arrivals, kind="stable")
@@ -197,9 +213,10 @@ class Server:
                 if s.busy or not waiting:
                     continue
                 take, atoms = [], 0
+                cap = s.cap if max_batch_atoms is None else max(1, min(s.cap, max_batch_atoms))
                 while waiting and len(take) < self.max_requests:
                     n = requests[waiting[0]][0].shape[0]
-                    if atoms + n > s.cap:
+                    if atoms + n > cap and take:
                         break
                     take.append(waiting.popleft())
                     atoms += n

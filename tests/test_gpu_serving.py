@@ -161,6 +161,16 @@ def test_server_closed_loop_and_poisson(P, model):
         assert res2[k]["E"] == res[k]["E"]
         np.testing.assert_array_equal(res2[k]["F"], res[k]["F"])
     assert st2["p99_ms"] >= st2["p50_ms"] > 0
+    # a cap on the atoms per batch: smaller batches (a request above the cap
+    # alone), the same results
+    sizes = [len(x) for x, _ in reqs]
+    res3, st3 = srv.run(reqs, max_batch_atoms=2000)
+    print("capped:", st3)
+    assert st3["batches"] > st["batches"]
+    assert st3["mean_batch_atoms"] <= max(2000, max(sizes))
+    for k in range(len(reqs)):
+        assert res3[k]["E"] == res[k]["E"]
+        np.testing.assert_array_equal(res3[k]["F"], res[k]["F"])
 
 
 def test_server_rejects_oversize_request_alone(P, model):
