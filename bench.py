@@ -649,15 +649,16 @@ def stride_sweep(P, cfg, params, x0, v0, box, steps):
     return rows
 
 
-SERVE_BATCH_ATOMS = 10000   # the Poisson (latency) phase's cap on atoms per batch
+SERVE_BATCH_ATOMS = 20000   # the Poisson (latency) phase's cap on atoms per batch
 
 
 def serving(P, model, nreq):
     """Continuous batching of nreq evaluation requests (periodic FCC-derived
     Cu cells, atom counts log-uniform in [32, 20000], sigma U[0.02, 0.15] A,
     0-5 % vacancies), FP32.  A closed loop (all requests at t = 0) gives the
-    saturated throughput; Poisson arrivals at 70 % of it give the latency
-    percentiles (arrival to results on the host)."""
+    saturated throughput; Poisson arrivals at 70 % of the saturated
+    throughput of the latency mode (batches of at most SERVE_BATCH_ATOMS
+    atoms) give the latency percentiles (arrival to results on the host)."""
     import synth
     from paper_2201_01446_amd.serve import Server, poisson_arrivals
     t = time.perf_counter()
@@ -665,11 +666,13 @@ def serving(P, model, nreq):
     gen_s = time.perf_counter() - t
     srv = Server(model, P.FP32, slots=3, hbm_budget=24 << 30)
     srv.run(reqs[:64])                          # warm-up
-    _, closed = srv.run(reqs)
-    rate = 0.7 * nreq / closed["wall_s"]
-    # latency mode: at most 10,000 atoms per batch, so that a burst of arrivals
-    # becomes several short batches rather than a few full slots that share
-    # the GPU and return late (median p99 over six arrival seeds 25 -> 8 ms)
+    _, closed = srv.run(reqs)                   # throughput: full slots
+    # latency mode: at most SERVE_BATCH_ATOMS atoms per batch, so that a burst
+    # of arrivals becomes several shorter batches rather than a few full slots
+    # that share the GPU and return late; Poisson arrivals at 70 % of this
+    # mode's own saturated throughput
+    _, capped = srv.run(reqs, max_batch_atoms=SERVE_BATCH_ATOMS)
+    rate = 0.7 * nreq / capped["wall_s"]
     _, pois = srv.run(reqs, poisson_arrivals(nreq, rate, seed=synth.SEED_SERVING + 1), max_batch_atoms=SERVE_BATCH_ATOMS)
     keep = ("atoms_per_s", "p50_ms", "p99_ms", "mean_ms", "mean_wait_ms", "mean_service_ms", "tail_wait_ms",
             "tail_service_ms", "tail_mean_atoms", "mean_atoms", "batches", "mean_batch_atoms", "wall_s")
@@ -677,7 +680,8 @@ def serving(P, model, nreq):
             "slot_atoms": closed["slot_atoms"], "precision": "fp32",
             "closed_loop": {k: round(closed[k], 4) for k in keep},
             "poisson": dict({k: round(pois[k], 4) for k in keep}, rate_req_per_s=round(rate, 2),
-                            max_batch_atoms=SERVE_BATCH_ATOMS),
+                            max_batch_atoms=SERVE_BATCH_ATOMS,
+                            saturated_atoms_per_s=round(capped["atoms_per_s"], 1)),
             "request_generation_s": round(gen_s, 2)}
 
 

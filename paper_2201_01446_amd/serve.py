@@ -89,6 +89,10 @@ class _Slot:
         self.stream = torch.cuda.Stream(device=device)
         self.cap = cap_atoms
         self.x_host = torch.empty((cap_atoms, 3), dtype=torch.float64).pin_memory()
+        # staging goes through this numpy view: a plain single-threaded copy
+        # (a torch slice assignment took up to 8 ms now and then, stalling
+        # the loop)
+        self.x_host_np = self.x_host.numpy()
         self.x_dev = torch.empty((cap_atoms, 3), dtype=torch.float64, device=device)
         self.E_host = torch.empty(max_requests, dtype=torch.float64).pin_memory()
         self.W_host = torch.empty((max_requests, 3, 3), dtype=torch.float64).pin_memory()
@@ -137,7 +141,7 @@ class Server:
         cells = []
         for rid, x, box in reqs:
             n = x.shape[0]
-            slot.x_host[off:off + n] = torch.from_numpy(np.ascontiguousarray(x))
+            slot.x_host_np[off:off + n] = x
             cells.append((n, box))
             off += n
         with torch.cuda.stream(slot.stream):
