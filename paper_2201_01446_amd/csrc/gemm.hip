@@ -119,13 +119,14 @@ struct Stage<0> {
 // XCD, whose L2 then serves the shared A rows.
 //
 // DT (first fitting layer, FP32 / FP64): A is the descriptor D = T<^T T
-// (Eq. 2) of each row's atom, formed from T while the stage is staged
+// (Eq. 2) of each row's atom, formed from T as each K stage is staged
 // instead of read from a stored D.  K then runs in the order
 // k' = b M< + a (a < M<, b < M), which the weights' copy V1tp follows, so a
 // stage covers whole columns b of D: a thread keeps the T<[k][a] of its
 // chunk's a in registers for the whole loop and loads the four T[k][b] of
-// each stage, one vector (T is stored by column: (T_0b, .., T_3b)).  Each element is summed as the embedding kernel sums D
-// (k = 0..3, fused multiply-adds from zero), so both forms are bit-equal.
+// each stage as one vector (T is stored by column: (T_0b, .., T_3b)).  Each
+// element is summed as the embedding kernel sums D (k = 0..3, fused
+// multiply-adds from zero), so both forms are bit-equal.
 template <typename TA, typename TR, int EPI, int TM, int TN, bool DT = false>
 __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const TA *__restrict__ A,
                                                  const TA *__restrict__ Bt, Epi e)
