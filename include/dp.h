@@ -255,6 +255,23 @@ dp_status dp_descriptor(dp_model *model, dp_nlist *nlist, int natoms, const doub
 dp_status dp_nlist_stats(dp_nlist *nlist, int *max_nei, int *n_sel_overflow, int *n_table_oob,
                          int *n_cap_overflow);
 
+/* The list's candidate arrays, for tests and inspection (paper Sec. 2.1,
+ * L_Rc(i) with the skin).  *natoms_h and *cap_h (host, required) receive the
+ * atom count N and the per-atom capacity C; call once with every array NULL
+ * to size them.  Each device array that is not NULL receives a copy (enqueued
+ * on `stream`, which is then synchronised):
+ *   cnt_d[N]       candidates of atom i (all (j, n) within rcut + skin)
+ *   nei_d[N * C]   row i, entries 0 .. cnt_i - 1: neighbor index j
+ *   shift_d[N * C] its image shift n, r_ij = x_j - x_i + n L, as three int8
+ *                  in bits 0-7 (x), 8-15 (y), 16-23 (z)
+ *   dist_d[N * C]  |r_ij| at build in FP32 (the sort key: ascending within
+ *                  a row, or within each type's run with several types)
+ *   rev_d[N * C]   (int16) the position of (i, -n) in j's row, -1 if absent
+ * Entries past cnt_i are undefined.  DP_ERR_ARG for a NULL list or count
+ * pointer. */
+dp_status dp_nlist_export(dp_nlist *nlist, int *natoms_h, int *cap_h, int *cnt_d, int *nei_d, int *shift_d,
+                          float *dist_d, short *rev_d, void *stream);
+
 /* Synchronises and returns what the evaluations on the list since its last
  * build have flagged: DP_ERR_NONFINITE (a non-finite energy, virial or
  * coordinate), DP_ERR_SKIN (an atom had moved skin/2 or more since the build,

@@ -54,6 +54,7 @@ _SIG = {
     "dp_energy_backward": [_vp, _vp, _i, _vp, _i, _i, _vp, _vp, _vp],
     "dp_nlist_stats": [_vp, _pi, _pi, _pi, _pi],
     "dp_nlist_check": [_vp],
+    "dp_nlist_export": [_vp, _pi, _pi, _vp, _vp, _vp, _vp, _vp, _vp],
     "dp_nve_run": [_vp, _pvp, _i, _vp, _vp, _vp, _vp, _vp, _d, _i, _i, _d, _i, _i, _vp, _vp],
     "dp_nve_continue": [_vp, _vp, _i, _vp, _vp, _vp, _d, _i, _i, _i, _i, _vp, _vp],
     "dp_batch_create": [_vp, _i, _i, _d, _pvp],

@@ -124,6 +124,22 @@ class NeighborList:
         check(lib.dp_nlist_stats(self.h, *[ctypes.byref(x) for x in v]))
         return dict(max_nei=v[0].value, sel_overflow=v[1].value, table_oob=v[2].value, cap_overflow=v[3].value)
 
+    def export(self):
+        """The candidate arrays (device tensors): cnt [N], and nei, shift
+        (three packed int8), dist (FP32) and rev (int16) [N, cap]."""
+        n, c = ctypes.c_int(), ctypes.c_int()
+        check(lib.dp_nlist_export(self.h, ctypes.byref(n), ctypes.byref(c), None, None, None, None, None, None))
+        N, C = n.value, c.value
+        dev = torch.device("cuda", torch.cuda.current_device())
+        out = dict(cnt=torch.empty(N, dtype=torch.int32, device=dev),
+                   nei=torch.empty(N, C, dtype=torch.int32, device=dev),
+                   shift=torch.empty(N, C, dtype=torch.int32, device=dev),
+                   dist=torch.empty(N, C, dtype=torch.float32, device=dev),
+                   rev=torch.empty(N, C, dtype=torch.int16, device=dev))
+        check(lib.dp_nlist_export(self.h, ctypes.byref(n), ctypes.byref(c), _ptr(out["cnt"]), _ptr(out["nei"]),
+                                  _ptr(out["shift"]), _ptr(out["dist"]), _ptr(out["rev"]), _stream()))
+        return out
+
     def __del__(self):
         if getattr(self, "h", None):
             lib.dp_nlist_destroy(self.h)

@@ -214,7 +214,7 @@ dp_status prepare_nlist(const dp_model *m, int natoms, const double *box, double
             if (nl->cell_cnt) DP_HIP(hipFree(nl->cell_cnt));
             nl->cell_atoms = nullptr;
             nl->cell_cnt = nullptr;
-            DP_HIP(hipMalloc(&nl->cell_atoms, sizeof(int) * (size_t)ncell * cellcap));
+            DP_HIP(hipMalloc(&nl->cell_atoms, sizeof(CellAtom) * (size_t)ncell * cellcap));
             DP_HIP(hipMalloc(&nl->cell_cnt, sizeof(int) * (size_t)ncell));
             nl->ncell_alloc = (size_t)ncell * cellcap;
         }
@@ -850,6 +850,26 @@ dp_status dp_nlist_check(dp_nlist *nl)
     return s != DP_OK ? s : check_build_flags(f);
 }
 
+dp_status dp_nlist_export(dp_nlist *nl, int *natoms, int *cap, int *cnt_d, int *nei_d, int *shift_d,
+                          float *dist_d, short *rev_d, void *stream)
+{
+    if (!nl || !natoms || !cap) return fail(DP_ERR_ARG, "NULL list or count pointer");
+    *natoms = nl->natoms;
+    *cap = nl->cap;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t n = (size_t)nl->natoms, nc = n * (size_t)nl->cap;
+    auto copy = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
+        return dst && bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st) : hipSuccess;
+    };
+    DP_HIP(copy(cnt_d, nl->cnt, sizeof(int) * n));
+    DP_HIP(copy(nei_d, nl->nei, sizeof(int) * nc));
+    DP_HIP(copy(shift_d, nl->shift, sizeof(int) * nc));
+    DP_HIP(copy(dist_d, nl->dist, sizeof(float) * nc));
+    DP_HIP(copy(rev_d, nl->rev, sizeof(short) * nc));
+    DP_HIP(hipStreamSynchronize(st));
+    return DP_OK;
+}
+
 dp_status dp_footprint_bytes(const dp_model *m, int natoms, size_t *bytes)
 {
     if (!m || natoms < 0 || !bytes) return fail(DP_ERR_ARG, "bad argument");
@@ -965,7 +985,7 @@ dp_status dp_batch_compute(dp_model *m, dp_batch *b, int nreq, const dp_request 
         if (nl->cell_atoms) DP_HIP(hipFree(nl->cell_atoms));
         if (nl->cell_cnt) DP_HIP(hipFree(nl->cell_cnt));
         size_t nc = std::max(cells_needed, (size_t)1);
-        DP_HIP(hipMalloc(&nl->cell_atoms, sizeof(int) * nc * cellcap));
+        DP_HIP(hipMalloc(&nl->cell_atoms, sizeof(CellAtom) * nc * cellcap));
         DP_HIP(hipMalloc(&nl->cell_cnt, sizeof(int) * nc));
         nl->ncell_alloc = nc * cellcap;
     }

@@ -57,6 +57,13 @@ struct FitWeights {
     void *V1tp = nullptr;
 };
 
+// An atom binned into a cell of the neighbor grid: its wrapped position,
+// index and type, read together by the candidate search.
+struct alignas(16) CellAtom {
+    double x, y, z;
+    int j, type;
+};
+
 }  // namespace dp
 
 struct dp_model {
@@ -97,7 +104,7 @@ struct dp_nlist {
     int cellcap = 0;
     size_t ncell_alloc = 0;
     int *cell_cnt = nullptr;
-    int *cell_atoms = nullptr;
+    dp::CellAtom *cell_atoms = nullptr;   // [ncell * cellcap]
     // wrapped positions and image index (int8 x3 packed) of every atom at build
     double *wpos = nullptr;
     int *wrap = nullptr;

@@ -50,11 +50,12 @@ __global__ void k_zero_int(int *p, long n)
     if (i < n) p[i] = 0;
 }
 
-// Wrap every atom into the box, record its image index and cell.
+// Wrap every atom into the box, record its image index and cell, and store
+// it (wrapped position, index, type) in its cell's slot.
 __global__ void k_bin(int n, const double *__restrict__ x, const int *__restrict__ types,
-                      double Lx, double Ly, double Lz, int ncx, int ncy, int ncz, int cellcap,
-                      double *__restrict__ wpos, int *__restrict__ wrap, int *__restrict__ cell_cnt,
-                      int *__restrict__ cell_atoms, int *__restrict__ flags)
+                      const int *__restrict__ key_types, double Lx, double Ly, double Lz, int ncx, int ncy,
+                      int ncz, int cellcap, double *__restrict__ wpos, int *__restrict__ wrap,
+                      int *__restrict__ cell_cnt, CellAtom *__restrict__ cell_atoms, int *__restrict__ flags)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -63,6 +64,7 @@ __global__ void k_bin(int n, const double *__restrict__ x, const int *__restrict
     double L[3] = {Lx, Ly, Lz};
     int nc[3] = {ncx, ncy, ncz};
     int k[3], c[3];
+    double w3[3];
     for (int a = 0; a < 3; a++) {
         double xa = x[3 * i + a];
         double fk = floor(xa / L[a]);
@@ -73,27 +75,83 @@ __global__ void k_bin(int n, const double *__restrict__ x, const int *__restrict
         if (fk > 60.0 || fk < -60.0) { atomicAdd(&flags[kFlagCapOverflow], 1); fk = 0.0; }
         k[a] = (int)fk;
         wpos[3 * i + a] = w;
+        w3[a] = w;
         int ci = (int)(w * nc[a] / L[a]);
         c[a] = ci < 0 ? 0 : (ci >= nc[a] ? nc[a] - 1 : ci);
     }
     wrap[i] = pack_shift(k[0], k[1], k[2]);
     int cell = (c[0] * ncy + c[1]) * ncz + c[2];
     int slot = atomicAdd(&cell_cnt[cell], 1);
-    if (slot < cellcap) cell_atoms[(long)cell * cellcap + slot] = i;
-    else atomicAdd(&flags[kFlagCellOverflow], 1);
+    if (slot < cellcap) {
+        CellAtom e;
+        e.x = w3[0];
+        e.y = w3[1];
+        e.z = w3[2];
+        e.j = i;
+        e.type = key_types ? key_types[i] : 0;
+        cell_atoms[(long)cell * cellcap + slot] = e;
+    } else {
+        atomicAdd(&flags[kFlagCellOverflow], 1);
+    }
 }
 
-// Sorts keys[0, P) ascending (P a power of two) with one 64-wide block.
-__device__ void bitonic_sort(unsigned long long *keys, int P)
+// Sorts keys[0, 64 KPL) ascending with one wave: a bitonic network over
+// the wave's registers, element e = lane KPL + r in register r of its lane.
+// Exchanges between elements fewer than KPL apart stay in the lane; the
+// others pair lane with lane ^ (distance / KPL) through a shuffle, each lane
+// keeping the minimum or the maximum of the two.  keys is read once and
+// written once (LDS); the caller synchronises around it.
+template <int KPL>
+__device__ void wave_sort(unsigned long long *keys)
 {
-    int lane = threadIdx.x;
+    const int lane = threadIdx.x;
+    unsigned long long v[KPL];
+#pragma unroll
+    for (int r = 0; r < KPL; r++) v[r] = keys[lane * KPL + r];
+#pragma unroll
+    for (int k = 2; k <= 64 * KPL; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= KPL) {
+                const int m = j / KPL;
+                const bool lower = (lane & m) == 0;
+#pragma unroll
+                for (int r = 0; r < KPL; r++) {
+                    const bool up = ((lane * KPL + r) & k) == 0;   // ascending run
+                    const unsigned long long o = __shfl_xor(v[r], m);
+                    const bool keep_min = up == lower;
+                    v[r] = (v[r] < o) == keep_min ? v[r] : o;
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < KPL; r++) {
+                    if (r & j) continue;
+                    const bool up = ((lane * KPL + r) & k) == 0;
+                    const unsigned long long a = v[r], b = v[r + j];
+                    const bool sw = (a > b) == up;
+                    v[r] = sw ? b : a;
+                    v[r + j] = sw ? a : b;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < KPL; r++) keys[lane * KPL + r] = v[r];
+}
+
+// The same network on keys[0, P) in LDS, for P above 512 (rows of more than
+// 512 candidates; sixteen keys per lane would triple the registers of the
+// kernels that sort).
+__device__ void lds_sort(unsigned long long *keys, int P)
+{
+    const int lane = threadIdx.x;
     for (int k = 2; k <= P; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
             for (int t = lane; t < P / 2; t += 64) {
-                int i0 = (t / j) * 2 * j + (t % j);
-                int i1 = i0 + j;
-                bool up = (i0 & k) == 0;
-                unsigned long long a = keys[i0], b = keys[i1];
+                const int i0 = ((t & ~(j - 1)) << 1) | (t & (j - 1));   // j is a power of two
+                const int i1 = i0 + j;
+                const bool up = (i0 & k) == 0;
+                const unsigned long long a = keys[i0], b = keys[i1];
                 if ((a > b) == up) {
                     keys[i0] = b;
                     keys[i1] = a;
@@ -101,6 +159,18 @@ __device__ void bitonic_sort(unsigned long long *keys, int P)
             }
             __syncthreads();
         }
+    }
+}
+
+// keys[0, P) ascending, P = 64 .. 1024 a power of two.
+__device__ void sort_keys(unsigned long long *keys, int P)
+{
+    switch (P) {
+    case 64: wave_sort<1>(keys); break;
+    case 128: wave_sort<2>(keys); break;
+    case 256: wave_sort<4>(keys); break;
+    case 512: wave_sort<8>(keys); break;
+    default: lds_sort(keys, P); break;
     }
 }
 
@@ -113,11 +183,12 @@ __device__ void finish_atom(int i, int cnt, int cap, unsigned long long *keys, c
         if (lane == 0) atomicAdd(&flags[kFlagCapOverflow], 1);
         cnt = cap;
     }
-    int P = 1;
+    int P = 64;   // <= the LDS array (the capacity rounded up to a power of two, >= 64)
     while (P < cnt) P <<= 1;
     for (int t = cnt + lane; t < P; t += 64) keys[t] = ~0ull;
     __syncthreads();
-    bitonic_sort(keys, P);
+    sort_keys(keys, P);
+    __syncthreads();
     int kix = (int)(signed char)(ki_packed & 0xFF), kiy = (int)(signed char)((ki_packed >> 8) & 0xFF),
         kiz = (int)(signed char)((ki_packed >> 16) & 0xFF);
     for (int t = lane; t < cnt; t += 64) {
@@ -133,6 +204,9 @@ __device__ void finish_atom(int i, int cnt, int cap, unsigned long long *keys, c
         out_shift[(long)i * cap + t] = pack_shift(sx + kix - kjx, sy + kiy - kjy, sz + kiz - kjz);
         out_dist[(long)i * cap + t] = __uint_as_float((unsigned)((key >> 31) & 0x7FFFFFFFu));
     }
+    // the rest of the row reads as beyond every candidate (the reverse
+    // search loads a fixed window that may reach past the count)
+    for (int t = cnt + lane; t < cap; t += 64) out_dist[(long)i * cap + t] = __builtin_huge_valf();
     if (out_tcnt) {
         int c[kMaxTypes] = {0, 0, 0, 0};
         for (int b = 0; b < cnt; b += 64) {
@@ -145,27 +219,29 @@ __device__ void finish_atom(int i, int cnt, int cap, unsigned long long *keys, c
     if (lane == 0) out_cnt[i] = cnt;
 }
 
-// One 64-thread block per atom: scan the (2R+1)^3 cell offsets.
+// Candidates of one atom per 64-thread block: each lane takes cell offsets
+// of the (2R+1)^3 window (two at most, R <= 2) and scans the atoms of that
+// cell, whose positions sit in the cell's own slots (no gather through an
+// index), four loads in flight at a time.
 __global__ void __launch_bounds__(64) k_candidates_cells(
     int n, const double *__restrict__ wpos, const int *__restrict__ wrap, double Lx, double Ly,
     double Lz, int ncx, int ncy, int ncz, int Rx, int Ry, int Rz, int cellcap,
-    const int *__restrict__ cell_cnt, const int *__restrict__ cell_atoms, double rcs2, int cap,
-    const int *__restrict__ types, int *__restrict__ out_cnt, int *__restrict__ out_nei,
-    int *__restrict__ out_shift, float *__restrict__ out_dist, int *__restrict__ out_tcnt,
-    int *__restrict__ flags, int joff)
+    const int *__restrict__ cell_cnt, const CellAtom *__restrict__ cell_atoms, double rcs2, int cap,
+    int *__restrict__ out_cnt, int *__restrict__ out_nei, int *__restrict__ out_shift,
+    float *__restrict__ out_dist, int *__restrict__ out_tcnt, int *__restrict__ flags, int joff)
 {
     HIP_DYNAMIC_SHARED(unsigned long long, keys)
     __shared__ int count;
     int i = xcd_item(blockIdx.x, gridDim.x);
     if (i >= n) return;   // the whole (one-wave) block
-    int lane = threadIdx.x;
+    const int lane = threadIdx.x;
     if (lane == 0) count = 0;
     __syncthreads();
-    double wi0 = wpos[3 * i], wi1 = wpos[3 * i + 1], wi2 = wpos[3 * i + 2];
-    int ci0 = min((int)(wi0 * ncx / Lx), ncx - 1), ci1 = min((int)(wi1 * ncy / Ly), ncy - 1),
-        ci2 = min((int)(wi2 * ncz / Lz), ncz - 1);
-    int wx = 2 * Rx + 1, wy = 2 * Ry + 1, wz = 2 * Rz + 1;
-    int noff = wx * wy * wz;
+    const double wi0 = wpos[3 * i], wi1 = wpos[3 * i + 1], wi2 = wpos[3 * i + 2];
+    const int ci0 = min((int)(wi0 * ncx / Lx), ncx - 1), ci1 = min((int)(wi1 * ncy / Ly), ncy - 1),
+              ci2 = min((int)(wi2 * ncz / Lz), ncz - 1);
+    const int wx = 2 * Rx + 1, wy = 2 * Ry + 1, wz = 2 * Rz + 1;
+    const int noff = wx * wy * wz;
     for (int oc = lane; oc < noff; oc += 64) {
         int dx = oc / (wy * wz) - Rx, dy = (oc / wz) % wy - Ry, dz = oc % wz - Rz;
         int cx = ci0 + dx, cy = ci1 + dy, cz = ci2 + dz;
@@ -176,17 +252,25 @@ __global__ void __launch_bounds__(64) k_candidates_cells(
         cx -= sx * ncx;
         cy -= sy * ncy;
         cz -= sz * ncz;
-        int cell = (cx * ncy + cy) * ncz + cz;
-        int m = min(cell_cnt[cell], cellcap);
-        double ox = sx * Lx - wi0, oy = sy * Ly - wi1, oz = sz * Lz - wi2;
-        int code = (sx + 2) * 25 + (sy + 2) * 5 + (sz + 2);
-        for (int t = 0; t < m; t++) {
-            int j = cell_atoms[(long)cell * cellcap + t];
-            double d0 = wpos[3 * j] + ox, d1 = wpos[3 * j + 1] + oy, d2 = wpos[3 * j + 2] + oz;
-            double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-            if (r2 < rcs2 && !(j == i && sx == 0 && sy == 0 && sz == 0)) {
-                int slot = atomicAdd(&count, 1);
-                if (slot < cap) keys[slot] = make_key(types ? types[j] : 0, (float)sqrt(r2), j, code);
+        const int cell = (cx * ncy + cy) * ncz + cz;
+        const int m = min(cell_cnt[cell], cellcap);
+        const double ox = sx * Lx - wi0, oy = sy * Ly - wi1, oz = sz * Lz - wi2;
+        const int code = (sx + 2) * 25 + (sy + 2) * 5 + (sz + 2);
+        const CellAtom *ca = cell_atoms + (long)cell * cellcap;
+        for (int t = 0; t < m; t += 4) {
+            CellAtom q[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (t + u < m) q[u] = ca[t + u];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                if (t + u >= m) break;
+                const double d0 = q[u].x + ox, d1 = q[u].y + oy, d2 = q[u].z + oz;
+                const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                if (r2 < rcs2 && !(q[u].j == i && code == 62 /* image (0, 0, 0) */)) {
+                    int slot = atomicAdd(&count, 1);
+                    if (slot < cap) keys[slot] = make_key(q[u].type, (float)sqrt(r2), q[u].j, code);
+                }
             }
         }
     }
@@ -338,9 +422,8 @@ dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, c
     }
     long ncell = (long)nl->nc[0] * nl->nc[1] * nl->nc[2];
     launch_fill_zero_int(nl->cell_cnt, ncell, st);
-    hipLaunchKernelGGL(k_bin, dim3(div_up(n, 256)), dim3(256), 0, st, n, x, check, nl->L[0], nl->L[1],
-                       nl->L[2], nl->nc[0], nl->nc[1], nl->nc[2], nl->cellcap,
-                       nl->wpos, nl->wrap, nl->cell_cnt,
+    hipLaunchKernelGGL(k_bin, dim3(div_up(n, 256)), dim3(256), 0, st, n, x, check, ktypes, nl->L[0], nl->L[1],
+                       nl->L[2], nl->nc[0], nl->nc[1], nl->nc[2], nl->cellcap, nl->wpos, nl->wrap, nl->cell_cnt,
                        nl->cell_atoms, nl->flags);
     int R[3];
     for (int a = 0; a < 3; a++) {
@@ -351,8 +434,8 @@ dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, c
     hipLaunchKernelGGL(k_candidates_cells, dim3(xcd_grid(n)), dim3(64), lds, st, n,
                        nl->wpos, nl->wrap, nl->L[0], nl->L[1],
                        nl->L[2], nl->nc[0], nl->nc[1], nl->nc[2], R[0], R[1], R[2], nl->cellcap,
-                       nl->cell_cnt, nl->cell_atoms, rcs2, nl->cap, ktypes, nl->cnt, nl->nei, nl->shift,
-                       nl->dist, tcnt, nl->flags, 0);
+                       nl->cell_cnt, nl->cell_atoms, rcs2, nl->cap, nl->cnt, nl->nei, nl->shift, nl->dist, tcnt,
+                       nl->flags, 0);
     launch_reverse(nl, 0, n, st);
     return launch_prefix(m, nl, x, st);
 }
@@ -384,12 +467,12 @@ dp_status launch_build_nlist_range(dp_nlist *nl, const double *x, int off, int n
     long ncell = (long)nc[0] * nc[1] * nc[2];
     if ((size_t)(ncell * nl->cellcap) > nl->ncell_alloc) return fail(DP_ERR_STATE, "cell grid too small");
     launch_fill_zero_int(nl->cell_cnt, ncell, st);
-    hipLaunchKernelGGL(k_bin, dim3(div_up(n, 256)), dim3(256), 0, st, n, xr, (const int *)nullptr, L[0], L[1], L[2],
-                       nc[0], nc[1], nc[2], nl->cellcap, nl->wpos + 3L * off, nl->wrap + off, nl->cell_cnt,
-                       nl->cell_atoms, nl->flags);
+    hipLaunchKernelGGL(k_bin, dim3(div_up(n, 256)), dim3(256), 0, st, n, xr, (const int *)nullptr,
+                       (const int *)nullptr, L[0], L[1], L[2], nc[0], nc[1], nc[2], nl->cellcap, nl->wpos + 3L * off,
+                       nl->wrap + off, nl->cell_cnt, nl->cell_atoms, nl->flags);
     hipLaunchKernelGGL(k_candidates_cells, dim3(xcd_grid(n)), dim3(64), lds, st, n, nl->wpos + 3L * off, nl->wrap + off, L[0],
                        L[1], L[2], nc[0], nc[1], nc[2], R[0], R[1], R[2], nl->cellcap, nl->cell_cnt, nl->cell_atoms,
-                       rcs2, nl->cap, (const int *)nullptr, cnt, nei, shift, dist, (int *)nullptr, nl->flags, off);
+                       rcs2, nl->cap, cnt, nei, shift, dist, (int *)nullptr, nl->flags, off);
     return DP_OK;
 }
 
@@ -465,15 +548,21 @@ __device__ inline int neg_shift(int v)
 
 // rev[i][c] = the slot of (i, -shift) in the list of j = nei[i][c], found
 // by distance in j's sorted list (a few float ulps of slack: j computed the
-// same distance from the other side), then a scan of the equal-distance
-// window.  With several types the search stays inside the run of i's type in
-// j's list (sorted by distance within the run).  The search starts at c's
-// rank within its own run (neighborhoods are alike, so the rank of r_ij in
-// both lists is similar) and gallops outward.  Each pair is searched once,
-// from its lower-indexed side (self-images: from the side with the larger
-// shift code), and both slots are written.  -1 when j's list lacks i, which
+// same distance from the other side), then a check of the entries in that
+// distance window.  With several types the search stays inside the run of
+// i's type in j's list (sorted by distance within the run).  Neighborhoods
+// are alike, so the rank of r_ij in both lists is similar: each lane loads
+// the kRevWindow entries of j's run around c's own rank at once, and when
+// they bracket the distance window (the common case: in a thermalised FCC
+// crystal the two ranks differ by at most 16 for all but about 1 pair in
+// 2000) the slot is found in them; otherwise the search gallops outward from
+// that rank and bisects.  Each pair is searched once, from its
+// lower-indexed side (self-images: from the side with the larger shift
+// code), and both slots are written.  -1 when j's list lacks i, which
 // happens only at the edge of the skin, far outside rcut.  One 64-thread
 // block per atom.
+constexpr int kRevWindow = 32;
+
 __device__ inline int run_start(const int *tcnt, int a, int ty)
 {
     int s = 0;
@@ -481,6 +570,7 @@ __device__ inline int run_start(const int *tcnt, int a, int ty)
     return s;
 }
 
+template <bool TYPED>
 __global__ void __launch_bounds__(64) k_reverse(int off, int n, int cap, const int *__restrict__ cnt,
                                                 const int *__restrict__ nei, const int *__restrict__ shift,
                                                 const float *__restrict__ dist, const int *__restrict__ type,
@@ -490,7 +580,7 @@ __global__ void __launch_bounds__(64) k_reverse(int off, int n, int cap, const i
     if (ib >= n) return;
     int i = off + ib;
     int nc = cnt[i];
-    int ti = type ? type[i] : 0;
+    int ti = TYPED ? type[i] : 0;
     for (int c = threadIdx.x; c < nc; c += 64) {
         long ic = (long)i * cap + c;
         int j = nei[ic];
@@ -502,12 +592,53 @@ __global__ void __launch_bounds__(64) k_reverse(int off, int n, int cap, const i
         float lo = __uint_as_float(rb > 8u ? rb - 8u : 0u), hi = __uint_as_float(rb + 8u);
         // j's run of type ti, and c's rank within i's run of j's type
         int j0 = 0, ncj = cnt[j], crel = c;
-        if (type) {
+        if (TYPED) {
             j0 = run_start(tcnt, j, ti);
             ncj = tcnt[(long)j * kMaxTypes + ti];
             crel = c - run_start(tcnt, i, type[j]);
         }
         const float *dj = dist + (long)j * cap + j0;
+        // the window [w0, w0 + kRevWindow) of the run around crel, inside the
+        // row's allocation (cap - j0 >= kRevWindow entries from j0, else the
+        // search below); entries at ncj and past it are loaded but not used
+        const int lim = cap - j0;
+        const int w0 = max(min(crel - kRevWindow / 2, lim - kRevWindow), 0);
+        const int nw = min(kRevWindow, ncj - w0);   // entries of the run in the window
+        // entries below lo and up to hi among the run's entries in the window
+        // (prefixes, as the run is sorted), counted on the bits of the
+        // non-negative distances (which order as integers)
+        int na = 0, nb = 0;
+        bool hit = false;
+        if (lim >= kRevWindow && nw > 0) {
+            unsigned wd[kRevWindow];
+#pragma unroll
+            for (int k = 0; k < kRevWindow; k++) wd[k] = __float_as_uint(dj[w0 + k]);
+            const unsigned ulo = __float_as_uint(lo), uhi = __float_as_uint(hi);
+#pragma unroll
+            for (int k = 0; k < kRevWindow; k++) {
+                // past the run: with one type the row's own +inf padding;
+                // with several the next type's run, taken as above every
+                // distance
+                const unsigned d = TYPED && k >= nw ? 0x7FFFFFFFu : wd[k];
+                na += d < ulo;
+                nb += d <= uhi;
+            }
+            // the window holds every entry of the distance window
+            hit = (w0 == 0 || na > 0) && (nb < nw || w0 + kRevWindow >= ncj);
+        }
+        if (hit) {
+            int found = -1;
+            for (int k = na; k < nb; k++) {
+                const long jt = (long)j * cap + j0 + w0 + k;
+                if (nei[jt] == i && shift[jt] == want) {
+                    found = j0 + w0 + k;
+                    break;
+                }
+            }
+            rev[ic] = (short)found;
+            if (found >= 0) rev[(long)j * cap + found] = (short)c;
+            continue;
+        }
         // first index a with dj[a] >= lo: gallop from min(crel, ncj - 1), then bisect
         int a, b;
         int p = crel < ncj ? crel : ncj - 1;
@@ -659,8 +790,12 @@ void launch_reverse(dp_nlist *nl, int off, int n, hipStream_t st)
     hipLaunchKernelGGL(k_fill_short, dim3(div_up(m, 256)), dim3(256), 0, st, nl->rev + (long)off * nl->cap, m,
                        (short)-1);
     const bool typed = nl->ntypes > 1;
-    hipLaunchKernelGGL(k_reverse, dim3(xcd_grid(n)), dim3(64), 0, st, off, n, nl->cap, nl->cnt, nl->nei, nl->shift,
-                       nl->dist, typed ? nl->type : nullptr, typed ? nl->tcnt : nullptr, nl->rev);
+    if (typed)
+        hipLaunchKernelGGL(k_reverse<true>, dim3(xcd_grid(n)), dim3(64), 0, st, off, n, nl->cap, nl->cnt, nl->nei,
+                           nl->shift, nl->dist, nl->type, nl->tcnt, nl->rev);
+    else
+        hipLaunchKernelGGL(k_reverse<false>, dim3(xcd_grid(n)), dim3(64), 0, st, off, n, nl->cap, nl->cnt, nl->nei,
+                           nl->shift, nl->dist, (const int *)nullptr, (const int *)nullptr, nl->rev);
 }
 
 void launch_force_gather(const dp_model *m, const dp_nlist *nl, int n, const double *x, int precision,

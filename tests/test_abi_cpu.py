@@ -62,6 +62,9 @@ def test_bad_arguments_are_rejected():
     assert _lib.lib.dp_model_destroy(None) == 0
     assert _lib.lib.dp_nlist_destroy(None) == 0
     assert _lib.lib.dp_nlist_check(None) == -1
+    n = ctypes.c_int()
+    assert _lib.lib.dp_nlist_export(None, ctypes.byref(n), ctypes.byref(n), None, None, None, None, None,
+                                    None) == -1
     assert _lib.lib.dp_tanh_table_download(None, None, None) == -1
     assert _lib.lib.dp_nve_run(None, None, 0, None, None, None, None, None, 1.0, 1, 1, 2.0, 0, 0, None,
                                None) == -1
