@@ -197,6 +197,7 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
             tl.ratom = nl->ratom;
         }
         tl.nlive = n;
+        tl.width = m->f1;
         for (int t = 0; t < kMaxTypes; t++) tl.b4[t] = m->b4[t];
         if (m->tanh_on)
             tl.tanh_tab = std::is_same<TR, double>::value ? (const void *)m->tanh_tab64 : (const void *)m->tanh_tab;
@@ -217,7 +218,13 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
             DP_TIMED("fit_bwd2", st, launch_gemm<TA, TR>(EPI_BWD, mr, kFitPad, ks * kFitPad, (const TA *)w.dz2o, (const TA *)fw.V2, e, st));
         }
         e = grouped(Epi{nullptr, nullptr, nullptr, nullptr, w.dDr, nullptr, nullptr}, kDdim, ks * kFitPad);
-        DP_TIMED("fit_bwd1", st, launch_gemm<TA, TR>(EPI_LIN, mr, kDdim, ks * kFitPad, (const TA *)w.dz1o, (const TA *)fw.V1, e, st));
+        // K = the net's width in whole K stages (dz1 and V1 are zero past it), rows kFitPad long
+        int k1 = ks * kFitPad;
+        if (ks == 1) {
+            k1 = (int)std::min<long>(kFitPad, round_up(m->f1, 128 / (long)sizeof(TA)));
+            e.kld = kFitPad;
+        }
+        DP_TIMED("fit_bwd1", st, launch_gemm<TA, TR>(EPI_LIN, mr, kDdim, k1, (const TA *)w.dz1o, (const TA *)fw.V1, e, st));
         if (PLAIN) {
             DP_TIMED("dT", st, launch_dT<TR>(n, (const TR *)w.dDr, (const TR *)w.T, (TR *)w.dT, st));
             if ((s = step_check("fitting_backward", st)) != DP_OK) return s;

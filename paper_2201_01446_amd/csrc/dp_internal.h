@@ -296,6 +296,9 @@ struct Epi {
     const void *dt_T = nullptr;
     const int *dt_ratom = nullptr;
     int dt_nlive = 0;
+    // row length of A and Bt (elements) when it exceeds K: the last kld - K
+    // elements of every row are zero padding that the product skips; 0: K
+    int kld = 0;
 };
 template <typename TA, typename TR>
 void launch_gemm(int epi, int M, int N, int K, const TA *A, const TA *Bt, const Epi &e, hipStream_t st);
@@ -327,6 +330,7 @@ struct TailLaunch {
     int nlive = 0;                          // one type: rows below nlive are atoms
     double b4[kMaxTypes] = {0, 0, 0, 0};
     const void *tanh_tab = nullptr;         // tanh table of the precision, or NULL
+    int width = kFitPad;                    // the net's width: the products run over K = width
 };
 template <typename T>
 void launch_fit_tail(int rows, const T *y1, const FitWeights &fw, const T *fb, const TailLaunch &tl, double *e_atom,

@@ -108,6 +108,7 @@ struct TailArgs {
     int nlive = 0;                // one type: rows below this are atoms
     double b4[kMaxTypes] = {0, 0, 0, 0};
     const void *tanh_tab = nullptr;   // table of the result type, or NULL (native tanh)
+    int nc = 0;                       // chunks of K per product (the net's width; the rest is zero padding)
 };
 
 constexpr int kTailPieces = kTailBChunk / 16 / kTailThreads;   // 16-byte pieces of a chunk per thread
@@ -152,10 +153,9 @@ __device__ inline void tail_chunk_mfma(const char *As, const char *Bc, typename 
 // the last reads of both.
 template <typename T>
 __device__ inline void tail_gemm(const char *As, char *Bs, const T *__restrict__ Bt,
-                                 typename MMT<T>::accv (&acc)[kTailCT], int tid, int rg, int ch, int m, int q)
+                                 typename MMT<T>::accv (&acc)[kTailCT], int tid, int rg, int ch, int m, int q, int NC)
 {
     using accv = typename MMT<T>::accv;
-    constexpr int NC = Tail<T>::NC;
 #pragma unroll
     for (int t = 0; t < kTailCT; t++) acc[t] = accv{0, 0, 0, 0};
     const int ar = rg * 16 + m;
@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(kTailThreads, kTailThreads / 128) k_fit_tail(c
     auto gel = [&](T *p, int ct, int i) -> T & { return p[(row0 + erow(i)) * kFitPad + ecol(ct)]; };
     accv acc[kTailCT];
     // y2 = y1 + tanh(y1 V2 + c2)
-    tail_gemm<T>(As, Bs, V2t + wo, acc, tid, rg, ch, m, q);
+    tail_gemm<T>(As, Bs, V2t + wo, acc, tid, rg, ch, m, q, ta.nc);
 #pragma unroll
     for (int ct = 0; ct < kTailCT; ct++) {
         T b = c2[ecol(ct)];
@@ -254,7 +254,7 @@ __global__ void __launch_bounds__(kTailThreads, kTailThreads / 128) k_fit_tail(c
     }
     __syncthreads();
     // t3 = tanh(y2 V3 + c3); E = (y2 + t3) . w4 + b4; dz3 = w4 (1 - t3^2)
-    tail_gemm<T>(As, Bs, V3t + wo, acc, tid, rg, ch, m, q);
+    tail_gemm<T>(As, Bs, V3t + wo, acc, tid, rg, ch, m, q, ta.nc);
     T es[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int ct = 0; ct < kTailCT; ct++) {
@@ -284,7 +284,7 @@ __global__ void __launch_bounds__(kTailThreads, kTailThreads / 128) k_fit_tail(c
     }
     __syncthreads();
     // dy2 = w4 + dz3 V3^T; dz2 = dy2 (1 - t2^2)
-    tail_gemm<T>(As, Bs, V3 + wo, acc, tid, rg, ch, m, q);
+    tail_gemm<T>(As, Bs, V3 + wo, acc, tid, rg, ch, m, q, ta.nc);
 #pragma unroll
     for (int ct = 0; ct < kTailCT; ct++) {
         T w = w4[ecol(ct)];
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(kTailThreads, kTailThreads / 128) k_fit_tail(c
     }
     __syncthreads();
     // dy1 = dy2 + dz2 V2^T; dz1 = dy1 (1 - y1^2), written out through LDS
-    tail_gemm<T>(As, Bs, V2 + wo, acc, tid, rg, ch, m, q);
+    tail_gemm<T>(As, Bs, V2 + wo, acc, tid, rg, ch, m, q, ta.nc);
 #pragma unroll
     for (int ct = 0; ct < kTailCT; ct++) {
 #pragma unroll
@@ -486,6 +486,8 @@ void launch_fit_tail(int rows, const T *y1, const FitWeights &fw, const T *fb, c
     ta.ratom = tl.ratom;
     ta.nlive = tl.nlive;
     ta.tanh_tab = tl.tanh_tab;
+    // K: the net's width in 64-byte chunks (the weights are zero past it)
+    ta.nc = std::min(Tail<T>::NC, div_up(tl.width * (int)sizeof(T), 64));
     if (tl.tanh_tab)
         hipLaunchKernelGGL((k_fit_tail<T, true>), dim3(rows / kTailBM), dim3(kTailThreads), 0, st, y1,
                            (const T *)fw.V2t, (const T *)fw.V3t, (const T *)fw.V3, (const T *)fw.V2, fb, ta, e_atom,

@@ -156,9 +156,9 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const TA *
     for (int g = 1; g < e.ntr; g++) ty += row0 >= e.trow[g] ? 1 : 0;
     Bt += ty * e.bstride;
 
-    const char *Ag = DT ? nullptr : reinterpret_cast<const char *>(A) + (long)row0 * K * sizeof(TA);
-    const char *Bg = reinterpret_cast<const char *>(Bt) + (long)col0 * K * sizeof(TA);
-    long ld = (long)K * sizeof(TA);
+    const long ld = (long)(e.kld > 0 ? e.kld : K) * sizeof(TA);   // row length (bytes)
+    const char *Ag = DT ? nullptr : reinterpret_cast<const char *>(A) + (long)row0 * ld;
+    const char *Bg = reinterpret_cast<const char *>(Bt) + (long)col0 * ld;
     // register staging of the next stage (all indices compile-time)
     Stage<LA> ra;
     Stage<LB> rb;
