@@ -218,10 +218,10 @@ dp_status run_t(const ComputeArgs &a, const WS &w, int np, const FitWeights &fw,
             DP_TIMED("fit_bwd2", st, launch_gemm<TA, TR>(EPI_BWD, mr, kFitPad, ks * kFitPad, (const TA *)w.dz2o, (const TA *)fw.V2, e, st));
         }
         e = grouped(Epi{nullptr, nullptr, nullptr, nullptr, w.dDr, nullptr, nullptr}, kDdim, ks * kFitPad);
-        // K = the net's width in whole K stages (dz1 and V1 are zero past it), rows kFitPad long
+        // K = the net's width in half K stages (dz1 and V1 are zero past it), rows kFitPad long
         int k1 = ks * kFitPad;
         if (ks == 1) {
-            k1 = (int)std::min<long>(kFitPad, round_up(m->f1, 128 / (long)sizeof(TA)));
+            k1 = (int)std::min<long>(kFitPad, round_up(m->f1, 64 / (long)sizeof(TA)));
             e.kld = kFitPad;
         }
         DP_TIMED("fit_bwd1", st, launch_gemm<TA, TR>(EPI_LIN, mr, kDdim, k1, (const TA *)w.dz1o, (const TA *)fw.V1, e, st));

@@ -297,7 +297,9 @@ struct Epi {
     const int *dt_ratom = nullptr;
     int dt_nlive = 0;
     // row length of A and Bt (elements) when it exceeds K: the last kld - K
-    // elements of every row are zero padding that the product skips; 0: K
+    // elements of every row are zero padding that the product skips; 0: K.
+    // K is a whole number of half stages (64 bytes of K); a K that ends in
+    // half a stage needs rows that reach the whole stage (kld)
     int kld = 0;
 };
 template <typename TA, typename TR>

@@ -168,7 +168,10 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const TA *
 #pragma unroll
         for (int b = 0; b < TN; b++) acc[a][b] = accv{0, 0, 0, 0};
 
-    int KT = K / BK;
+    // K in whole stages, or ending in half a stage (K a multiple of BK / 2:
+    // the last stage is staged whole, its second half unused)
+    const int KT = (K + BK - 1) / BK;
+    const int kg_last = K % BK ? 1 : 2;   // K groups of the last stage
     // DT: chunk rr of this thread is row (tid / 8) + 32 rr of the tile and
     // elements VEC (tid mod 8) .. + VEC of the stage, i.e. a = that mod M<
     // and one b per stage; rows without an atom (padding) get D = 0
@@ -241,6 +244,7 @@ __global__ void __launch_bounds__(256) k_gemm_nt(int M, int N, int K, const TA *
         }
 #pragma unroll
         for (int kg = 0; kg < 2; kg++) {
+            if (kt == KT - 1 && kg >= kg_last) break;
             int off = kg * 64 + q * 16;   // bytes: group kg of 4*VEC elements, lane group q
             u4v fa[TM], fb[TN];
 #pragma unroll
