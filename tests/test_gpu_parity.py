@@ -135,6 +135,22 @@ def test_cu500_fp64_vs_untabulated_oracle(P, model, cu_cfg, cu_params):
     assert rmse(got["F"], ref["F"]) < 1e-10
 
 
+@pytest.mark.parametrize("width", [8, 100, 256])
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_fitting_widths(P, width, precision):
+    """Fitting nets narrower than the 256-column padding, and one at it: the
+    products run over the net's width (partial weight chunks and half K
+    stages at 8 and 100), with the padding's zero weights never read."""
+    cfg = dict(synth.copper_model_config(), fit=(width, width, width))
+    p = synth.model_params(cfg)
+    m = P.Model(cfg, p).tabulate(S_MAX, H, TAIL, H_TAIL)
+    tab = oracle.Table(cfg, p, S_MAX, H, TAIL, H_TAIL)
+    x, box = synth.copper(3, 0.1, 61)
+    ref = oracle.evaluate(cfg, p, x, box, table=tab)
+    got, _ = run(P, m, x, box, precision)
+    check_against(ref, got, precision, len(x))
+
+
 @pytest.mark.parametrize("ncell", [2, 3])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_small_periodic_cells(P, model, cu_cfg, cu_params, otab, ncell, precision):
