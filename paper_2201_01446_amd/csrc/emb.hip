@@ -451,6 +451,18 @@ __global__ void __launch_bounds__(256) k_emb_bwd(int natoms, EnvArgs A, const re
     p += kSegRound * 24 * sizeof(real);
     int *seg = reinterpret_cast<int *>(p);
     bool live = i < natoms;
+    // this lane's part of dE/dD (see below) into registers first: its loads
+    // stream from HBM while the neighbor scan runs
+    constexpr int APG = kMlt / NG;
+    const int g = lane / GL, l = lane % GL;
+    real dv[APG][CPL];
+    if (live) {
+        const real *dDi = dD + fit_row(A, i) * kDdim;
+#pragma unroll
+        for (int qa = 0; qa < APG; qa++)
+#pragma unroll
+            for (int c = 0; c < CPL; c++) dv[qa][c] = dDi[(g * APG + qa) * kM + l + GL * c];
+    }
     int nn = 0;
     if (live) nn = load_env<real>(i, A, L, lane);
     __syncthreads();
@@ -463,10 +475,7 @@ __global__ void __launch_bounds__(256) k_emb_bwd(int natoms, EnvArgs A, const re
     // reduction, added at the lane that owns column b = a; the groups'
     // partials are then summed and group 0 parks dT in LDS.
     {
-        constexpr int APG = kMlt / NG;
-        int g = lane / GL, l = lane % GL;
         const V4<real> *Ti = reinterpret_cast<const V4<real> *>(T) + (long)i * kM;   // T by column
-        const real *dDi = dD + fit_row(A, i) * kDdim;
         real dt[4][CPL], tc[4][CPL];
 #pragma unroll
         for (int c = 0; c < CPL; c++) {
@@ -491,7 +500,7 @@ __global__ void __launch_bounds__(256) k_emb_bwd(int natoms, EnvArgs A, const re
             for (int k = 0; k < 4; k++) s2[k] = 0;
 #pragma unroll
             for (int c = 0; c < CPL; c++) {
-                real v = dDi[a0 * kM + l + GL * c];
+                real v = dv[qa][c];
 #pragma unroll
                 for (int k = 0; k < 4; k++) {
                     dt[k][c] = fma(v, ta[k], dt[k][c]);
