@@ -397,7 +397,8 @@ inline long fit_rows(long atoms, int ntypes) { return round_up(atoms, kRowPad) +
 // assigns every atom its fitting-net row (synchronises once).
 dp_status build_type_layout(dp_nlist *nl, const int *types, hipStream_t st);
 // Reverse slots of the candidate lists of atoms [off, off + n) (after a build).
-void launch_reverse(dp_nlist *nl, int off, int n, hipStream_t st);
+// uniq: no list holds two images of one atom (the slot match needs only the index)
+void launch_reverse(dp_nlist *nl, int off, int n, hipStream_t st, bool uniq = false);
 // F_i = (F_i as written by the backward: sum_j dE_i/dr_ij) - sum over the
 // atoms j that list i of dE_j/dr_ji, read from the pair gradients at the
 // reverse slot (rec / rcnt: the forward's neighbor records); deterministic

@@ -417,7 +417,7 @@ dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, c
     if (!nl->periodic) {
         hipLaunchKernelGGL(k_candidates_open, dim3(xcd_grid(n)), dim3(64), lds, st, n, x, check, ktypes, rcs2,
                            nl->cap, nl->cnt, nl->nei, nl->shift, nl->dist, tcnt, nl->flags, 0);
-        launch_reverse(nl, 0, n, st);
+        launch_reverse(nl, 0, n, st, true);   // open: every image shift is zero
         return launch_prefix(m, nl, x, st);
     }
     long ncell = (long)nl->nc[0] * nl->nc[1] * nl->nc[2];
@@ -436,7 +436,10 @@ dp_status launch_build_nlist(const dp_model *m, dp_nlist *nl, const double *x, c
                        nl->L[2], nl->nc[0], nl->nc[1], nl->nc[2], R[0], R[1], R[2], nl->cellcap,
                        nl->cell_cnt, nl->cell_atoms, rcs2, nl->cap, nl->cnt, nl->nei, nl->shift, nl->dist, tcnt,
                        nl->flags, 0);
-    launch_reverse(nl, 0, n, st);
+    // edges of at least 2 (rcut + skin): a list holds at most one image of
+    // any atom, so j's slot for i is the one whose index is i
+    const bool uniq = nl->L[0] >= 2 * nl->rc_build && nl->L[1] >= 2 * nl->rc_build && nl->L[2] >= 2 * nl->rc_build;
+    launch_reverse(nl, 0, n, st, uniq);
     return launch_prefix(m, nl, x, st);
 }
 
@@ -559,8 +562,10 @@ __device__ inline int neg_shift(int v)
 // that rank and bisects.  Each pair is searched once, from its
 // lower-indexed side (self-images: from the side with the larger shift
 // code), and both slots are written.  -1 when j's list lacks i, which
-// happens only at the edge of the skin, far outside rcut.  One 64-thread
-// block per atom.
+// happens only at the edge of the skin, far outside rcut.  uniq (box edges
+// of at least 2 (rcut + skin), or no box): a list holds at most one image of
+// any atom, so an entry of the window is i's slot when its index is i (the
+// image shift is not read).  One 64-thread block per atom.
 constexpr int kRevWindow = 32;
 
 __device__ inline int run_start(const int *tcnt, int a, int ty)
@@ -574,7 +579,7 @@ template <bool TYPED>
 __global__ void __launch_bounds__(64) k_reverse(int off, int n, int cap, const int *__restrict__ cnt,
                                                 const int *__restrict__ nei, const int *__restrict__ shift,
                                                 const float *__restrict__ dist, const int *__restrict__ type,
-                                                const int *__restrict__ tcnt, short *__restrict__ rev)
+                                                const int *__restrict__ tcnt, short *__restrict__ rev, bool uniq)
 {
     int ib = xcd_item(blockIdx.x, gridDim.x);
     if (ib >= n) return;
@@ -630,7 +635,7 @@ __global__ void __launch_bounds__(64) k_reverse(int off, int n, int cap, const i
             int found = -1;
             for (int k = na; k < nb; k++) {
                 const long jt = (long)j * cap + j0 + w0 + k;
-                if (nei[jt] == i && shift[jt] == want) {
+                if (nei[jt] == i && (uniq || shift[jt] == want)) {
                     found = j0 + w0 + k;
                     break;
                 }
@@ -673,7 +678,7 @@ __global__ void __launch_bounds__(64) k_reverse(int off, int n, int cap, const i
         int found = -1;
         for (int t = a; t < ncj && dj[t] <= hi; t++) {
             long jt = (long)j * cap + j0 + t;
-            if (nei[jt] == i && shift[jt] == want) {
+            if (nei[jt] == i && (uniq || shift[jt] == want)) {
                 found = j0 + t;
                 break;
             }
@@ -781,7 +786,7 @@ __global__ void __launch_bounds__(256) k_force_gather(int n, EnvArgs A, const sh
 
 }  // namespace
 
-void launch_reverse(dp_nlist *nl, int off, int n, hipStream_t st)
+void launch_reverse(dp_nlist *nl, int off, int n, hipStream_t st, bool uniq)
 {
     if (n <= 0) return;
     // every slot starts at -1: a pair is searched from one side only, so a
@@ -792,10 +797,10 @@ void launch_reverse(dp_nlist *nl, int off, int n, hipStream_t st)
     const bool typed = nl->ntypes > 1;
     if (typed)
         hipLaunchKernelGGL(k_reverse<true>, dim3(xcd_grid(n)), dim3(64), 0, st, off, n, nl->cap, nl->cnt, nl->nei,
-                           nl->shift, nl->dist, nl->type, nl->tcnt, nl->rev);
+                           nl->shift, nl->dist, nl->type, nl->tcnt, nl->rev, uniq);
     else
         hipLaunchKernelGGL(k_reverse<false>, dim3(xcd_grid(n)), dim3(64), 0, st, off, n, nl->cap, nl->cnt, nl->nei,
-                           nl->shift, nl->dist, (const int *)nullptr, (const int *)nullptr, nl->rev);
+                           nl->shift, nl->dist, (const int *)nullptr, (const int *)nullptr, nl->rev, uniq);
 }
 
 void launch_force_gather(const dp_model *m, const dp_nlist *nl, int n, const double *x, int precision,
