@@ -250,28 +250,38 @@ __device__ int scan_candidates(int i, const EnvArgs &A, NbrLDS<real> L, int lane
     const int *shf = A.shift + (long)i * A.cap;
     const real rty = (real)ty;
     int n_in = 0;
-    // two chunks of 64 candidates per pass: the index, shift and position
-    // loads of both are in flight together
-    for (int b = 0; b < ct; b += 128) {
-        int ka = c0 + b + lane, kb = ka + 64;
-        bool la = b + lane < ct, lb = b + 64 + lane < ct;
-        int ja = la ? nei[ka] : 0, sa = la ? shf[ka] : 0;
-        int jb = lb ? nei[kb] : 0, sb = lb ? shf[kb] : 0;
-        double a0 = 0, a1 = 0, a2 = 0, b0 = 0, b1 = 0, b2 = 0;
-        bool ina = la && within_cut(A.x, ja, xi0, xi1, xi2, sa, L0, L1, L2, A.rc2, a0, a1, a2);
-        bool inb = lb && within_cut(A.x, jb, xi0, xi1, xi2, sb, L0, L1, L2, A.rc2, b0, b1, b2);
+    // four chunks of 64 candidates per pass: the index, shift and position
+    // loads of all of them are in flight together (the ~218 candidates of a
+    // copper atom's scan prefix in one pass)
+    constexpr int NCH = 4;
+    for (int b = 0; b < ct; b += 64 * NCH) {
+        int kk[NCH], jj[NCH], ss[NCH];
+        bool ll[NCH], inn[NCH];
+        double dd[NCH][3];
 #pragma unroll
-        for (int h = 0; h < 2; h++) {
-            bool in = h ? inb : ina;
-            int k = h ? kb : ka, j = h ? jb : ja;
-            double d0 = h ? b0 : a0, d1 = h ? b1 : a1, d2 = h ? b2 : a2;
+        for (int h = 0; h < NCH; h++) {
+            kk[h] = c0 + b + 64 * h + lane;
+            ll[h] = b + 64 * h + lane < ct;
+            jj[h] = ll[h] ? nei[kk[h]] : 0;
+            ss[h] = ll[h] ? shf[kk[h]] : 0;
+        }
+#pragma unroll
+        for (int h = 0; h < NCH; h++) {
+            dd[h][0] = dd[h][1] = dd[h][2] = 0;
+            inn[h] = ll[h] && within_cut(A.x, jj[h], xi0, xi1, xi2, ss[h], L0, L1, L2, A.rc2, dd[h][0], dd[h][1],
+                                         dd[h][2]);
+        }
+#pragma unroll
+        for (int h = 0; h < NCH; h++) {
+            const bool in = inn[h];
+            const double d0 = dd[h][0], d1 = dd[h][1], d2 = dd[h][2];
             unsigned long long mask = __ballot(in);
             int q = n_in + __popcll(mask & ((1ull << lane) - 1ull));
             if (in && q < lim) {
                 int pos = base + q;
                 (MODE == ENV_BWD ? L.Dv : L.R)[pos] = V4<real>{(real)d0, (real)d1, (real)d2, rty};
-                if (MODE != ENV_FWD) L.j[pos] = j;
-                if (MODE == ENV_FWD && A.rec) put_record<real>(A, i, pos, d0, d1, d2, slot_code(k, ty));
+                if (MODE != ENV_FWD) L.j[pos] = jj[h];
+                if (MODE == ENV_FWD && A.rec) put_record<real>(A, i, pos, d0, d1, d2, slot_code(kk[h], ty));
             }
             n_in += __popcll(mask);
         }
