@@ -375,11 +375,23 @@ __device__ int load_env(int i, const EnvArgs &A, NbrLDS<real> L, int lane)
 {
     int nn = A.rcnt[i] & ~kTruncBit;
     const V4<real> *rec = reinterpret_cast<const V4<real> *>(A.rec) + (long)i * A.sel;
-    for (int k = lane; k < nn; k += 64) {
-        V4<real> r = rec[k];
-        int code = record_slot(r.w);
-        L.Dv[k] = V4<real>{r.x, r.y, r.z, (real)(code >> 24)};
-        L.j[k] = code & 0xFFFFFF;
+    // four records per lane in flight
+    for (int k0 = 0; k0 < nn; k0 += 256) {
+        V4<real> r[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            int k = k0 + 64 * u + lane;
+            if (k < nn) r[u] = rec[k];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            int k = k0 + 64 * u + lane;
+            if (k < nn) {
+                int code = record_slot(r[u].w);
+                L.Dv[k] = V4<real>{r[u].x, r[u].y, r[u].z, (real)(code >> 24)};
+                L.j[k] = code & 0xFFFFFF;
+            }
+        }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
