@@ -122,11 +122,14 @@ def test_copper_list_108k_sampled(P, cu_cfg, cu_params):
     assert 330 < cnt.mean() < 380
 
 
-def test_water_lists_grouped_by_type(P):
-    """Two types (rcut 6 A): rows grouped by neighbor type, sorted within."""
+@pytest.mark.parametrize("nrep", [1, 2])
+def test_water_lists_grouped_by_type(P, nrep):
+    """Two types (rcut 6 A): rows grouped by neighbor type, sorted within.
+    One cell (12.4 A edge, below 2 (rcut + skin)) holds several images of
+    some atoms in a list; two cells at most one."""
     cfg = synth.water_model_config()
     p = synth.model_params(cfg)
-    x, t, box = synth.water(2, sigma=0.02)
+    x, t, box = synth.water(nrep, sigma=0.02)
     check_list(P, cfg, p, x, box, types=t, sample=64, seed=4)
 
 
